@@ -1,0 +1,216 @@
+/*
+ * pafem -- partial-assembly (sum-factorized) H1 mass and diffusion operators on
+ * tensor-product hexahedral meshes, and the Jacobi-preconditioned CG solve
+ * built on them, for AMD Instinct MI355X (gfx950).
+ *
+ * The operator follows the finite element operator decomposition of the paper
+ * (figure "finite element operator decomposition": A = P^T G^T B^T D B G P).
+ * On one GPU P is the identity; G is the element restriction (called E here,
+ * to keep G free for the basis-gradient table), B/G are 1D basis value and
+ * derivative tables applied by sum factorization, and D is the pointwise
+ * quadrature data that partial assembly stores (section "State-of-the-art
+ * performance on exascale platforms and AMD GPUs", the partial assembly
+ * level).  The diagonal for Jacobi is computed by sum factorization (section
+ * "Matrix-free solvers for high-order finite elements").
+ *
+ * Discretization fixed by this library (the paper does not state them):
+ *   - reference element [0,1]^3, trilinear geometry from the 8 element corners;
+ *   - nodal Lagrange basis of order p (1..8) on the p+1 Gauss-Lobatto-Legendre
+ *     points per direction;
+ *   - q Gauss-Legendre points per direction, q = p+2 (the only value accepted);
+ *   - global dofs numbered lattice-lexicographically, x fastest: dof (I,J,K) of
+ *     the (nx p+1) x (ny p+1) x (nz p+1) node lattice has number
+ *     I + (nx p+1) (J + (ny p+1) K); elements e = ex + nx (ey + ny ez); local
+ *     element dof l = a + (p+1) (b + (p+1) c); quadrature point
+ *     qx + q (qy + q qz);
+ *   - essential (Dirichlet) dofs: every node on the boundary of the mesh block.
+ *
+ * Conventions
+ *   - Every call returns int: PAFEM_OK (0) or a negative PAFEM_ERR_* code;
+ *     pafem_last_error() then holds a message (per calling thread).
+ *   - Handles are opaque, owned by the library, released by *_destroy.  A
+ *     space keeps its mesh alive and an operator its space: destroy in reverse
+ *     order of creation (children first).
+ *   - Vectors passed as "_dev" are device pointers owned by the caller,
+ *     contiguous, of the element type stated; the library never frees them.
+ *     "_host" pointers are host memory, copied before the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Calls that take a stream only enqueue work on it unless the
+ *     comment says "synchronous".
+ *   - A context created with device = -1 is host-only: mesh, space and map
+ *     queries work without a GPU; anything that touches device memory returns
+ *     PAFEM_ERR_UNSUPPORTED.
+ */
+#ifndef PAFEM_H
+#define PAFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define PAFEM_OK 0
+#define PAFEM_ERR_INVALID_ARG (-1)
+#define PAFEM_ERR_OUT_OF_MEMORY (-2)
+#define PAFEM_ERR_HIP (-3)
+#define PAFEM_ERR_NOT_CONVERGED (-4)
+#define PAFEM_ERR_UNSUPPORTED (-5)
+#define PAFEM_ERR_NO_DEVICE (-6)
+
+/* ---- operator kinds, precisions, modes ------------------------------------ */
+#define PAFEM_MASS 0      /* M_ij = sum_q w rho detJ phi_i phi_j            */
+#define PAFEM_DIFFUSION 1 /* K_ij = sum_q w k detJ (J^-T dphi_i).(J^-T dphi_j) */
+
+#define PAFEM_FP64 1 /* vectors double, FP64 quadrature data and contractions */
+#define PAFEM_FP32 2 /* vectors float, FP32 quadrature data (rounded copy)     */
+
+#define PAFEM_SCATTER_ATOMIC 0        /* E^T by FP64/FP32 atomic adds (fast, run-to-run rounding differences) */
+#define PAFEM_SCATTER_DETERMINISTIC 1 /* E^T by E-vector + per-dof ordered sum (bitwise reproducible) */
+
+#define PAFEM_SOLVE_PLAIN_FP64 0 /* Jacobi-PCG entirely in FP64 */
+#define PAFEM_SOLVE_IR_FP32 1    /* FP64 defect correction around an FP32 Jacobi-PCG */
+
+/* ---- opaque handles -------------------------------------------------------- */
+typedef struct pafem_ctx pafem_ctx;
+typedef struct pafem_mesh pafem_mesh;
+typedef struct pafem_space pafem_space;
+typedef struct pafem_op pafem_op;
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next pafem call on the same thread. */
+const char* pafem_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int pafem_version(void);
+
+/* ---- context ---------------------------------------------------------------- */
+/* Bind to HIP device `device` (>= 0), or host-only with device = -1.
+ * Errors: NO_DEVICE if the device does not exist, HIP on runtime failure. */
+int pafem_ctx_create(int device, pafem_ctx** out);
+int pafem_ctx_destroy(pafem_ctx* ctx);
+
+/* ---- mesh -------------------------------------------------------------------- */
+/* Structured hexahedral mesh of nx*ny*nz elements (each >= 1) whose corner
+ * vertices are given, x index fastest: vert_xyz_host[((k (ny+1) + j) (nx+1) + i) * 3 + d].
+ * Element (ex,ey,ez) has corners (ex+i, ey+j, ez+k), i,j,k in {0,1}; the map
+ * from [0,1]^3 is trilinear.  The array is copied (to the device too, for a
+ * GPU context).  Orientation is checked later, at operator assembly. */
+int pafem_mesh_create_structured(pafem_ctx* ctx, int nx, int ny, int nz,
+                                 const double* vert_xyz_host, pafem_mesh** out);
+int pafem_mesh_destroy(pafem_mesh* mesh);
+
+/* ---- order p: H1 space and its integer maps ----------------------------------- */
+/* Order p in 1..8 (INVALID_ARG otherwise).  Builds the element restriction E
+ * (int32, [ne][(p+1)^3]), its transpose in CSR form and the essential-dof list;
+ * ne*(p+1)^3 and the dof count must each fit in int32 (INVALID_ARG otherwise). */
+int pafem_space_create(pafem_mesh* mesh, int p, pafem_space** out);
+int pafem_space_destroy(pafem_space* space);
+int64_t pafem_space_ndofs(const pafem_space* space);   /* (nx p+1)(ny p+1)(nz p+1), or -1 */
+int64_t pafem_space_nelems(const pafem_space* space);  /* nx ny nz, or -1 */
+int64_t pafem_space_num_ess(const pafem_space* space); /* number of essential dofs, or -1 */
+/* Copy E (row e = element, column l = local dof) into E_host[ne*(p+1)^3]. */
+int pafem_space_get_restriction(const pafem_space* space, int32_t* E_host);
+/* Copy E^T as CSR: offsets_host[ndofs+1], indices_host[ne*(p+1)^3]; the
+ * indices of dof i are the E-vector positions e*(p+1)^3+l with E[e][l] = i,
+ * ascending. */
+int pafem_space_get_restriction_transpose(const pafem_space* space, int32_t* offsets_host,
+                                          int32_t* indices_host);
+/* Copy the ascending essential-dof list into out_host[num_ess]. */
+int pafem_space_get_ess_dofs(const pafem_space* space, int32_t* out_host);
+
+/* ---- quadrature: 1D tables (host, no GPU needed) ------------------------------ */
+/* Gauss-Lobatto-Legendre nodes (p+1), Gauss-Legendre points and weights (q) on
+ * [0,1], and B[qq][a] = l_a(x_qq), G[qq][a] = l_a'(x_qq) (row-major [q][p+1]).
+ * Any output pointer may be NULL.  1 <= p <= 8, 1 <= q <= 12. */
+int pafem_basis_tables(int p, int q, double* gll_nodes, double* gl_points, double* gl_weights,
+                       double* B, double* G);
+
+/* ---- operator --------------------------------------------------------------- */
+/* Create a MASS or DIFFUSION operator on `space` with q1d points per direction
+ * (0 = default p+2; any other value but p+2 gives UNSUPPORTED).  The
+ * coefficient defaults to the constant 1.  Nothing is computed until
+ * pafem_op_assemble. */
+int pafem_op_create(pafem_space* space, int kind, int q1d, pafem_op** out);
+int pafem_op_destroy(pafem_op* op);
+int pafem_op_q1d(const pafem_op* op);
+/* Physical coordinates of the quadrature points, xyz_dev[ne][3][q^3] (double). */
+int pafem_op_qpoint_coords(pafem_op* op, double* xyz_dev, void* stream);
+/* Coefficient (rho for MASS, k for DIFFUSION): a constant, values at the
+ * quadrature points k_dev[ne][q^3] (copied into library memory on `stream`),
+ * or the built-in k = 1 + amp sin(2 pi x) evaluated on the device. Takes effect
+ * at the next pafem_op_assemble. */
+int pafem_op_set_coefficient_const(pafem_op* op, double c);
+int pafem_op_set_coefficient_qpts(pafem_op* op, const double* k_dev, void* stream);
+int pafem_op_set_coefficient_sinx(pafem_op* op, double amp);
+/* Compute the quadrature data D on the device (synchronous).
+ * MASS: D[e][0][qpt] = w rho detJ.  DIFFUSION: D[e][0..5][qpt] = the upper
+ * triangle xx,xy,xz,yy,yz,zz of w k adj(J) adj(J)^T / detJ.  FP64 is always
+ * built; prec_mask | PAFEM_FP32 also keeps an FP32 rounded copy.
+ * INVALID_ARG if detJ <= 0 at any quadrature point (inverted element). */
+int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream);
+/* Device bytes the quadrature data occupies for prec_mask (or -1). */
+int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask);
+/* Copy the stored quadrature data of precision `prec` into dst_dev
+ * ([ne][C][q^3], C = 1 or 6, double or float). */
+int pafem_op_get_qdata(pafem_op* op, int prec, void* dst_dev, void* stream);
+/* Choose how E^T sums element contributions (default ATOMIC). */
+int pafem_op_set_scatter_mode(pafem_op* op, int mode);
+
+/* y = A x.  prec selects double (PAFEM_FP64) or float (PAFEM_FP32, needs the
+ * FP32 copy) vectors of length ndofs; x and y must not alias.
+ * constrained = 0: the plain assembled operator.  constrained = 1: rows and
+ * columns of essential dofs replaced by the identity (y_ess = x_ess, free rows
+ * see x with essential entries zeroed). */
+int pafem_op_apply(pafem_op* op, int prec, const void* x_dev, void* y_dev, int constrained,
+                   void* stream);
+/* d = diag(A) by sum factorization (double, ndofs); constrained = 1 puts 1 on
+ * essential dofs.  Bitwise reproducible. */
+int pafem_op_diagonal(pafem_op* op, double* d_dev, int constrained, void* stream);
+
+/* ---- right-hand side ------------------------------------------------------------ */
+/* b_i = sum_e sum_q w detJ f(x_q) phi_i(x_q) with the op's quadrature rule and
+ * geometry; f_qpts_dev[ne][q^3] holds f at the quadrature points (as returned
+ * by pafem_op_qpoint_coords), or NULL for the built-in f = 3 pi^2
+ * sin(pi x) sin(pi y) sin(pi z).  Essential entries of b are set to 0.
+ * Bitwise reproducible. */
+int pafem_rhs_assemble(pafem_op* op, const double* f_qpts_dev, double* b_dev, void* stream);
+
+/* ---- solve ------------------------------------------------------------------- */
+typedef struct {
+  int mode;          /* PAFEM_SOLVE_PLAIN_FP64 or PAFEM_SOLVE_IR_FP32 */
+  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for plain CG) */
+  double inner_rtol; /* IR: relative tolerance of each FP32 inner solve (e.g. 1e-4) */
+  int maxit;         /* plain: max CG iterations; IR: max inner iterations per solve */
+  int max_outer;     /* IR: max refinement steps */
+  int check_every;   /* host reads the residual every this many iterations (>= 1) */
+} pafem_solve_opts;
+
+typedef struct {
+  int iterations;       /* plain: CG iterations; IR: total inner iterations */
+  int outer_iterations; /* IR: refinement steps (0 for plain) */
+  double rel_res;       /* final relative residual the stopping test saw */
+  double true_rel_res;  /* ||b - A x||_2 / ||b||_2 recomputed in FP64 after the solve */
+  double seconds;       /* wall time of the solve on the host clock */
+} pafem_solve_stats;
+
+/* Solve A x = b for the constrained operator of `op` (DIFFUSION or MASS) with
+ * Jacobi preconditioning; x_dev holds the initial guess on entry (its
+ * essential entries must equal b's) and the solution on return.
+ * Synchronous.  NOT_CONVERGED if the iteration limit is hit (x then holds the
+ * last iterate and stats are filled).  IR_FP32 needs the FP32 quadrature copy. */
+int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem_solve_opts* opts,
+                   pafem_solve_stats* stats, void* stream);
+
+/* ---- reductions (exposed for testing the CG building blocks) --------------------- */
+/* result_dev[0] = sum_i x[i] y[i] over n doubles, fixed-order two-stage
+ * reduction (bitwise reproducible for a given n). */
+int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x_dev, const double* y_dev,
+              double* result_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAFEM_H */

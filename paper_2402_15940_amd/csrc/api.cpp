@@ -1,0 +1,512 @@
+// C ABI of the pafem library: object lifetimes, argument checking, dispatch.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "internal.h"
+
+namespace pafem {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+namespace {
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+#define CHECK_ARG(cond, msg)             \
+  do {                                   \
+    if (!(cond)) {                       \
+      set_error(msg);                    \
+      return PAFEM_ERR_INVALID_ARG;      \
+    }                                    \
+  } while (0)
+
+int need_device(const Ctx* c) {
+  if (c->host_only) {
+    set_error("operation needs a GPU context (created with device >= 0)");
+    return PAFEM_ERR_UNSUPPORTED;
+  }
+  PAFEM_TRY_HIP(hipSetDevice(c->device));
+  return PAFEM_OK;
+}
+
+template <typename T>
+int upload(DevBuf& b, const T* src, size_t n) {
+  PAFEM_TRY(b.ensure(n * sizeof(T)));
+  if (n) PAFEM_TRY_HIP(hipMemcpy(b.ptr, src, n * sizeof(T), hipMemcpyHostToDevice));
+  return PAFEM_OK;
+}
+
+GeomArgs geom(const Op* op, const double* pts, const double* wts) {
+  const Mesh* m = op->space->mesh;
+  GeomArgs g;
+  g.verts = m->d_verts.as<double>();
+  g.nx = m->nx;
+  g.ny = m->ny;
+  g.nz = m->nz;
+  g.ne = op->space->ne;
+  g.q = op->q;
+  g.pts = pts;
+  g.wts = wts;
+  return g;
+}
+
+// Device table layout (T = double or float): B[q][n] | G[q][n] | pts[q] | wts[q]
+template <typename T>
+const T* tabB(const DevBuf& b) { return b.as<T>(); }
+template <typename T>
+const T* tabG(const DevBuf& b, int q, int n) { return b.as<T>() + q * n; }
+inline const double* tabPts(const DevBuf& b, int q, int n) { return b.as<double>() + 2 * q * n; }
+inline const double* tabWts(const DevBuf& b, int q, int n) {
+  return b.as<double>() + 2 * q * n + q;
+}
+
+}  // namespace
+
+int ensure_et(Space* sp) {
+  if (sp->d_et_off.ptr) return PAFEM_OK;
+  PAFEM_TRY(upload(sp->d_et_off, sp->et_off.data(), sp->et_off.size()));
+  PAFEM_TRY(upload(sp->d_et_idx, sp->et_idx.data(), sp->et_idx.size()));
+  return PAFEM_OK;
+}
+
+template <typename T>
+int apply_impl(Op* op, const T* x, T* y, int constrained, const int* skip, hipStream_t s) {
+  Space* sp = op->space;
+  const int n = sp->p + 1;
+  const DevBuf& tab = std::is_same<T, double>::value ? op->d_tab64 : op->d_tab32;
+  ApplyArgs<T> a;
+  a.x = x;
+  a.y = y;
+  a.yE = nullptr;
+  a.E = sp->d_E.as<int32_t>();
+  a.ess_mask = sp->d_ess_mask.as<uint8_t>();
+  a.qd = std::is_same<T, double>::value ? (const T*)op->d_qd64.ptr : (const T*)op->d_qd32.ptr;
+  a.B = tabB<T>(tab);
+  a.G = tabG<T>(tab, op->q, n);
+  a.ne = sp->ne;
+  a.constrained = constrained;
+  a.skip = skip;
+  if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
+    PAFEM_TRY(ensure_et(sp));
+    PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
+    a.yE = op->d_evec.as<T>();
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, a, s));
+    PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(), sp->d_et_idx.as<int32_t>(),
+                                      a.ess_mask, constrained, x, y, sp->ndofs, skip, s));
+  } else {
+    // zero y with a kernel (not a memset) so the sequence can sit in a captured graph
+    PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
+    if (constrained)
+      PAFEM_TRY_HIP(launch_set_ess<T>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), x, T(0), y,
+                                      skip, s));
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_ATOMIC, a, s));
+  }
+  return PAFEM_OK;
+}
+
+int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
+  Space* sp = op->space;
+  const int n = sp->p + 1;
+  PAFEM_TRY(ensure_et(sp));
+  PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
+  PAFEM_TRY_HIP(launch_diag_elem(op->kind, sp->p, op->q, op->d_qd64.as<double>(),
+                                 tabB<double>(op->d_tab64), tabG<double>(op->d_tab64, op->q, n),
+                                 sp->ne, op->d_evec.as<double>(), s));
+  // constrained rows get 1 (x = nullptr means 0, so set them afterwards)
+  PAFEM_TRY_HIP(launch_gather_et<double>(op->d_evec.as<double>(), sp->d_et_off.as<int32_t>(),
+                                         sp->d_et_idx.as<int32_t>(), sp->d_ess_mask.as<uint8_t>(),
+                                         0, nullptr, d, sp->ndofs, nullptr, s));
+  return PAFEM_OK;
+}
+
+template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t);
+template int apply_impl<float>(Op*, const float*, float*, int, const int*, hipStream_t);
+
+}  // namespace pafem
+
+using namespace pafem;
+
+struct pafem_ctx : Ctx {};
+struct pafem_mesh : Mesh {};
+struct pafem_space : Space {};
+struct pafem_op : Op {};
+
+extern "C" {
+
+const char* pafem_last_error(void) { return g_err.c_str(); }
+
+int pafem_version(void) { return 100; }
+
+int pafem_ctx_create(int device, pafem_ctx** out) {
+  clear_error();
+  CHECK_ARG(out != nullptr, "out is NULL");
+  *out = nullptr;
+  CHECK_ARG(device >= -1, "device must be >= -1");
+  auto* c = new pafem_ctx();
+  c->device = device;
+  c->host_only = device < 0;
+  if (!c->host_only) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || device >= count) {
+      delete c;
+      set_error("HIP device " + std::to_string(device) + " not available (" +
+                std::to_string(count) + " visible)");
+      return PAFEM_ERR_NO_DEVICE;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+      delete c;
+      set_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+      return PAFEM_ERR_HIP;
+    }
+  }
+  *out = c;
+  return PAFEM_OK;
+}
+
+int pafem_ctx_destroy(pafem_ctx* ctx) {
+  if (ctx) {
+    if (!ctx->host_only) (void)hipSetDevice(ctx->device);
+    delete ctx;
+  }
+  return PAFEM_OK;
+}
+
+int pafem_mesh_create_structured(pafem_ctx* ctx, int nx, int ny, int nz,
+                                 const double* vert_xyz_host, pafem_mesh** out) {
+  clear_error();
+  CHECK_ARG(ctx && out && vert_xyz_host, "NULL argument");
+  *out = nullptr;
+  CHECK_ARG(nx >= 1 && ny >= 1 && nz >= 1, "nx, ny, nz must be >= 1");
+  const int64_t nv = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  CHECK_ARG((int64_t)nx * ny * nz < std::numeric_limits<int32_t>::max(), "too many elements");
+  for (int64_t i = 0; i < nv * 3; ++i)
+    CHECK_ARG(std::isfinite(vert_xyz_host[i]), "vertex coordinates must be finite");
+  auto* m = new pafem_mesh();
+  m->ctx = ctx;
+  m->nx = nx;
+  m->ny = ny;
+  m->nz = nz;
+  m->verts.assign(vert_xyz_host, vert_xyz_host + nv * 3);
+  if (!ctx->host_only) {
+    int rc = need_device(ctx);
+    if (rc == PAFEM_OK) rc = upload(m->d_verts, m->verts.data(), m->verts.size());
+    if (rc != PAFEM_OK) {
+      delete m;
+      return rc;
+    }
+  }
+  *out = m;
+  return PAFEM_OK;
+}
+
+int pafem_mesh_destroy(pafem_mesh* mesh) {
+  delete mesh;
+  return PAFEM_OK;
+}
+
+int pafem_space_create(pafem_mesh* mesh, int p, pafem_space** out) {
+  clear_error();
+  CHECK_ARG(mesh && out, "NULL argument");
+  *out = nullptr;
+  CHECK_ARG(p >= 1 && p <= kMaxP, "p must be in 1..8");
+  const int64_t n = p + 1;
+  const int64_t ne = (int64_t)mesh->nx * mesh->ny * mesh->nz;
+  const int64_t ndofs =
+      ((int64_t)mesh->nx * p + 1) * ((int64_t)mesh->ny * p + 1) * ((int64_t)mesh->nz * p + 1);
+  CHECK_ARG(ne * n * n * n < std::numeric_limits<int32_t>::max(),
+            "ne*(p+1)^3 must fit in int32");
+  CHECK_ARG(ndofs < std::numeric_limits<int32_t>::max(), "ndofs must fit in int32");
+  auto* sp = new pafem_space();
+  sp->mesh = mesh;
+  sp->p = p;
+  sp->ne = ne;
+  sp->ndofs = ndofs;
+  build_restriction(mesh->nx, mesh->ny, mesh->nz, p, sp->E);
+  build_restriction_transpose(sp->E, ndofs, sp->et_off, sp->et_idx);
+  build_essential(mesh->nx, mesh->ny, mesh->nz, p, sp->ess, sp->ess_mask);
+  if (!mesh->ctx->host_only) {
+    int rc = need_device(mesh->ctx);
+    if (rc == PAFEM_OK) rc = upload(sp->d_E, sp->E.data(), sp->E.size());
+    if (rc == PAFEM_OK) rc = upload(sp->d_ess, sp->ess.data(), sp->ess.size());
+    if (rc == PAFEM_OK) rc = upload(sp->d_ess_mask, sp->ess_mask.data(), sp->ess_mask.size());
+    if (rc != PAFEM_OK) {
+      delete sp;
+      return rc;
+    }
+  }
+  *out = sp;
+  return PAFEM_OK;
+}
+
+int pafem_space_destroy(pafem_space* space) {
+  delete space;
+  return PAFEM_OK;
+}
+
+int64_t pafem_space_ndofs(const pafem_space* s) { return s ? s->ndofs : -1; }
+int64_t pafem_space_nelems(const pafem_space* s) { return s ? s->ne : -1; }
+int64_t pafem_space_num_ess(const pafem_space* s) { return s ? (int64_t)s->ess.size() : -1; }
+
+int pafem_space_get_restriction(const pafem_space* s, int32_t* E_host) {
+  clear_error();
+  CHECK_ARG(s && E_host, "NULL argument");
+  std::memcpy(E_host, s->E.data(), s->E.size() * sizeof(int32_t));
+  return PAFEM_OK;
+}
+
+int pafem_space_get_restriction_transpose(const pafem_space* s, int32_t* off, int32_t* idx) {
+  clear_error();
+  CHECK_ARG(s && off && idx, "NULL argument");
+  std::memcpy(off, s->et_off.data(), s->et_off.size() * sizeof(int32_t));
+  std::memcpy(idx, s->et_idx.data(), s->et_idx.size() * sizeof(int32_t));
+  return PAFEM_OK;
+}
+
+int pafem_space_get_ess_dofs(const pafem_space* s, int32_t* out) {
+  clear_error();
+  CHECK_ARG(s && out, "NULL argument");
+  std::memcpy(out, s->ess.data(), s->ess.size() * sizeof(int32_t));
+  return PAFEM_OK;
+}
+
+int pafem_basis_tables(int p, int q, double* nodes, double* pts, double* wts, double* B,
+                       double* G) {
+  clear_error();
+  CHECK_ARG(p >= 1 && p <= kMaxP, "p must be in 1..8");
+  CHECK_ARG(q >= 1 && q <= kMaxQ, "q must be in 1..12");
+  std::vector<double> nd(p + 1), x(q), w(q), b(q * (p + 1)), g(q * (p + 1));
+  gll_nodes(p, nd.data());
+  gauss_legendre(q, x.data(), w.data());
+  lagrange_tables(p + 1, nd.data(), q, x.data(), b.data(), g.data());
+  if (nodes) std::memcpy(nodes, nd.data(), nd.size() * sizeof(double));
+  if (pts) std::memcpy(pts, x.data(), x.size() * sizeof(double));
+  if (wts) std::memcpy(wts, w.data(), w.size() * sizeof(double));
+  if (B) std::memcpy(B, b.data(), b.size() * sizeof(double));
+  if (G) std::memcpy(G, g.data(), g.size() * sizeof(double));
+  return PAFEM_OK;
+}
+
+int pafem_op_create(pafem_space* space, int kind, int q1d, pafem_op** out) {
+  clear_error();
+  CHECK_ARG(space && out, "NULL argument");
+  *out = nullptr;
+  CHECK_ARG(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, "kind must be MASS or DIFFUSION");
+  const int p = space->p;
+  const int q = q1d == 0 ? p + 2 : q1d;
+  if (q != p + 2) {
+    set_error("only q1d = p + 2 is supported");
+    return PAFEM_ERR_UNSUPPORTED;
+  }
+  PAFEM_TRY(need_device(space->mesh->ctx));
+  auto* op = new pafem_op();
+  op->space = space;
+  op->kind = kind;
+  op->q = q;
+  op->ncomp = kind == PAFEM_DIFFUSION ? 6 : 1;
+  const int n = p + 1;
+  std::vector<double> nd(n), x(q), w(q), tab(2 * q * n + 2 * q);
+  gll_nodes(p, nd.data());
+  gauss_legendre(q, x.data(), w.data());
+  lagrange_tables(n, nd.data(), q, x.data(), tab.data(), tab.data() + q * n);
+  std::memcpy(tab.data() + 2 * q * n, x.data(), q * sizeof(double));
+  std::memcpy(tab.data() + 2 * q * n + q, w.data(), q * sizeof(double));
+  std::vector<float> tab32(tab.size());
+  for (size_t i = 0; i < tab.size(); ++i) tab32[i] = (float)tab[i];
+  int rc = upload(op->d_tab64, tab.data(), tab.size());
+  if (rc == PAFEM_OK) rc = upload(op->d_tab32, tab32.data(), tab32.size());
+  if (rc == PAFEM_OK) rc = op->d_flag.ensure(sizeof(int));
+  if (rc != PAFEM_OK) {
+    delete op;
+    return rc;
+  }
+  *out = op;
+  return PAFEM_OK;
+}
+
+int pafem_op_destroy(pafem_op* op) {
+  if (op) {
+    (void)hipSetDevice(op->space->mesh->ctx->device);
+    delete op;
+  }
+  return PAFEM_OK;
+}
+
+int pafem_op_q1d(const pafem_op* op) { return op ? op->q : -1; }
+
+int pafem_op_qpoint_coords(pafem_op* op, double* xyz, void* stream) {
+  clear_error();
+  CHECK_ARG(op && xyz, "NULL argument");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  const int n = op->space->p + 1;
+  GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, n), tabWts(op->d_tab64, op->q, n));
+  PAFEM_TRY_HIP(launch_qpoint_coords(g, xyz, S(stream)));
+  return PAFEM_OK;
+}
+
+int pafem_op_set_coefficient_const(pafem_op* op, double c) {
+  clear_error();
+  CHECK_ARG(op, "NULL argument");
+  CHECK_ARG(std::isfinite(c), "coefficient must be finite");
+  op->coef_kind = COEF_CONST;
+  op->coef_value = c;
+  return PAFEM_OK;
+}
+
+int pafem_op_set_coefficient_qpts(pafem_op* op, const double* k, void* stream) {
+  clear_error();
+  CHECK_ARG(op && k, "NULL argument");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  const size_t n = (size_t)op->space->ne * op->q * op->q * op->q;
+  PAFEM_TRY(op->d_coef.ensure(n * sizeof(double)));
+  PAFEM_TRY_HIP(hipMemcpyAsync(op->d_coef.ptr, k, n * sizeof(double), hipMemcpyDeviceToDevice,
+                               S(stream)));
+  op->coef_kind = COEF_QPTS;
+  return PAFEM_OK;
+}
+
+int pafem_op_set_coefficient_sinx(pafem_op* op, double amp) {
+  clear_error();
+  CHECK_ARG(op, "NULL argument");
+  CHECK_ARG(std::isfinite(amp), "amplitude must be finite");
+  op->coef_kind = COEF_SINX;
+  op->coef_value = amp;
+  return PAFEM_OK;
+}
+
+int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask) {
+  if (!op) return -1;
+  const int64_t n = op->space->ne * (int64_t)op->q * op->q * op->q * op->ncomp;
+  int64_t b = n * 8;
+  if (prec_mask & PAFEM_FP32) b += n * 4;
+  return b;
+}
+
+int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
+  clear_error();
+  CHECK_ARG(op, "NULL argument");
+  CHECK_ARG((prec_mask & ~(PAFEM_FP64 | PAFEM_FP32)) == 0, "unknown precision bits");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  const size_t n = (size_t)op->space->ne * op->q * op->q * op->q * op->ncomp;
+  PAFEM_TRY(op->d_qd64.ensure(n * sizeof(double)));
+  float* q32 = nullptr;
+  if (prec_mask & PAFEM_FP32) {
+    PAFEM_TRY(op->d_qd32.ensure(n * sizeof(float)));
+    q32 = op->d_qd32.as<float>();
+  }
+  const int nn = op->space->p + 1;
+  GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, nn), tabWts(op->d_tab64, op->q, nn));
+  hipStream_t s = S(stream);
+  PAFEM_TRY_HIP(hipMemsetAsync(op->d_flag.ptr, 0, sizeof(int), s));
+  PAFEM_TRY_HIP(launch_qdata(g, op->kind, op->coef_kind, op->coef_value, op->d_coef.as<double>(),
+                             op->d_qd64.as<double>(), q32, op->d_flag.as<int>(), s));
+  int flag = 0;
+  PAFEM_TRY_HIP(hipMemcpyAsync(&flag, op->d_flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
+  op->have64 = true;
+  op->have32 = q32 != nullptr;
+  op->have_dinv = false;
+  if (flag) {
+    op->have64 = op->have32 = false;
+    set_error("non-positive Jacobian determinant at a quadrature point (inverted element)");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  return PAFEM_OK;
+}
+
+int pafem_op_get_qdata(pafem_op* op, int prec, void* dst, void* stream) {
+  clear_error();
+  CHECK_ARG(op && dst, "NULL argument");
+  CHECK_ARG(prec == PAFEM_FP64 || prec == PAFEM_FP32, "prec must be FP64 or FP32");
+  const bool have = prec == PAFEM_FP64 ? op->have64 : op->have32;
+  CHECK_ARG(have, "quadrature data of that precision not assembled");
+  const size_t n = (size_t)op->space->ne * op->q * op->q * op->q * op->ncomp;
+  const void* src = prec == PAFEM_FP64 ? op->d_qd64.ptr : op->d_qd32.ptr;
+  PAFEM_TRY_HIP(hipMemcpyAsync(dst, src, n * (prec == PAFEM_FP64 ? 8 : 4), hipMemcpyDeviceToDevice,
+                               S(stream)));
+  return PAFEM_OK;
+}
+
+int pafem_op_set_scatter_mode(pafem_op* op, int mode) {
+  clear_error();
+  CHECK_ARG(op, "NULL argument");
+  CHECK_ARG(mode == PAFEM_SCATTER_ATOMIC || mode == PAFEM_SCATTER_DETERMINISTIC,
+            "unknown scatter mode");
+  op->scatter_mode = mode;
+  return PAFEM_OK;
+}
+
+int pafem_op_apply(pafem_op* op, int prec, const void* x, void* y, int constrained,
+                   void* stream) {
+  clear_error();
+  CHECK_ARG(op && x && y, "NULL argument");
+  CHECK_ARG(x != y, "x and y must not alias");
+  CHECK_ARG(constrained == 0 || constrained == 1, "constrained must be 0 or 1");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  if (prec == PAFEM_FP64) {
+    CHECK_ARG(op->have64, "operator not assembled");
+    return apply_impl<double>(op, (const double*)x, (double*)y, constrained, nullptr, S(stream));
+  }
+  if (prec == PAFEM_FP32) {
+    CHECK_ARG(op->have32, "FP32 quadrature data not assembled");
+    return apply_impl<float>(op, (const float*)x, (float*)y, constrained, nullptr, S(stream));
+  }
+  set_error("prec must be PAFEM_FP64 or PAFEM_FP32");
+  return PAFEM_ERR_INVALID_ARG;
+}
+
+int pafem_op_diagonal(pafem_op* op, double* d, int constrained, void* stream) {
+  clear_error();
+  CHECK_ARG(op && d, "NULL argument");
+  CHECK_ARG(constrained == 0 || constrained == 1, "constrained must be 0 or 1");
+  CHECK_ARG(op->have64, "operator not assembled");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  hipStream_t s = S(stream);
+  PAFEM_TRY(diagonal_impl(op, d, constrained, s));
+  if (constrained)
+    PAFEM_TRY_HIP(launch_set_ess<double>(op->space->d_ess.as<int32_t>(),
+                                         (int64_t)op->space->ess.size(), nullptr, 1.0, d, nullptr,
+                                         s));
+  return PAFEM_OK;
+}
+
+int pafem_rhs_assemble(pafem_op* op, const double* f_q, double* b, void* stream) {
+  clear_error();
+  CHECK_ARG(op && b, "NULL argument");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  Space* sp = op->space;
+  const int n = sp->p + 1;
+  PAFEM_TRY(ensure_et(sp));
+  PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
+  GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, n), tabWts(op->d_tab64, op->q, n));
+  hipStream_t s = S(stream);
+  PAFEM_TRY_HIP(launch_rhs_elem(g, sp->p, tabB<double>(op->d_tab64), f_q, op->d_evec.as<double>(), s));
+  PAFEM_TRY_HIP(launch_gather_et<double>(op->d_evec.as<double>(), sp->d_et_off.as<int32_t>(),
+                                         sp->d_et_idx.as<int32_t>(), sp->d_ess_mask.as<uint8_t>(),
+                                         1, nullptr, b, sp->ndofs, nullptr, s));
+  return PAFEM_OK;
+}
+
+int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x, const double* y, double* result,
+              void* stream) {
+  clear_error();
+  CHECK_ARG(ctx && x && y && result, "NULL argument");
+  CHECK_ARG(n >= 0, "n must be >= 0");
+  PAFEM_TRY(need_device(ctx));
+  const int nb = reduce_blocks(n);
+  PAFEM_TRY(ctx->scratch.ensure(nb * sizeof(double)));
+  hipStream_t s = S(stream);
+  PAFEM_TRY_HIP(launch_dot_partial<double>(x, y, n, ctx->scratch.as<double>(), nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(ctx->scratch.as<double>(), nb, 1, result, s));
+  return PAFEM_OK;
+}
+
+}  // extern "C"

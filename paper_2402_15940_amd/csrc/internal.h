@@ -1,0 +1,253 @@
+// Internal declarations of the pafem library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pafem.h"
+
+namespace pafem {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+void clear_error();
+
+// Status carrying a pafem error code; converted to the C return value.
+#define PAFEM_TRY_HIP(expr)                                                             \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      ::pafem::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));            \
+      return _e == hipErrorOutOfMemory ? PAFEM_ERR_OUT_OF_MEMORY : PAFEM_ERR_HIP;       \
+    }                                                                                   \
+  } while (0)
+
+#define PAFEM_TRY(expr)          \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != PAFEM_OK) return _rc; \
+  } while (0)
+
+// Device allocation owned by a library object.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  // (Re)allocate at least `n` bytes; keeps the buffer if it is already large enough.
+  int ensure(size_t n) {
+    if (n <= bytes && ptr) return PAFEM_OK;
+    release();
+    if (n == 0) return PAFEM_OK;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      set_error("hipMalloc(" + std::to_string(n) + " bytes): " + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? PAFEM_ERR_OUT_OF_MEMORY : PAFEM_ERR_HIP;
+    }
+    bytes = n;
+    return PAFEM_OK;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(ptr); }
+};
+
+// ---------------------------------------------------------------------------
+// host-side setup (basis.cpp, mesh.cpp)
+// ---------------------------------------------------------------------------
+constexpr int kMaxP = 8;
+constexpr int kMaxQ = 12;
+
+// Gauss-Lobatto-Legendre nodes on [0,1] (p+1 of them), by Newton's method on the
+// Legendre three-term recurrence.
+void gll_nodes(int p, double* x);
+// Gauss-Legendre points and weights on [0,1] (weights sum to 1), Newton on P_q.
+void gauss_legendre(int q, double* x, double* w);
+// B[i][a] = l_a(x_i), G[i][a] = l_a'(x_i) for the Lagrange basis on `nodes`,
+// evaluated with the barycentric form.
+void lagrange_tables(int n, const double* nodes, int m, const double* x, double* B, double* G);
+
+// Structured-lattice element restriction and friends.
+void build_restriction(int nx, int ny, int nz, int p, std::vector<int32_t>& E);
+void build_restriction_transpose(const std::vector<int32_t>& E, int64_t ndofs,
+                                 std::vector<int32_t>& off, std::vector<int32_t>& idx);
+void build_essential(int nx, int ny, int nz, int p, std::vector<int32_t>& ess,
+                     std::vector<uint8_t>& mask);
+
+// ---------------------------------------------------------------------------
+// library objects
+// ---------------------------------------------------------------------------
+struct Ctx {
+  int device = -1;
+  bool host_only = true;
+  DevBuf scratch;  // reduction partials for pafem_dot
+};
+
+struct Mesh {
+  Ctx* ctx = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  std::vector<double> verts;
+  DevBuf d_verts;
+};
+
+struct Space {
+  Mesh* mesh = nullptr;
+  int p = 0;
+  int64_t ndofs = 0, ne = 0;
+  std::vector<int32_t> E, et_off, et_idx, ess;
+  std::vector<uint8_t> ess_mask;
+  DevBuf d_E, d_et_off, d_et_idx, d_ess, d_ess_mask;
+};
+
+enum CoefKind { COEF_CONST = 0, COEF_QPTS = 1, COEF_SINX = 2 };
+
+// Device-resident state of one Jacobi-PCG solve; all scalars live on the GPU so
+// an iteration needs no host round trip.
+struct CgState {
+  double rz;       // r . z
+  double pAp;      // p . A p
+  double rr;       // r . r
+  double alpha, beta;
+  double rr_stop;  // stop when rr <= rr_stop
+  double bb;       // b . b
+  int iter;
+  int done;
+  int maxit;
+  int pad;
+};
+
+struct Op {
+  Space* space = nullptr;
+  int kind = PAFEM_DIFFUSION;
+  int q = 0;
+  int ncomp = 6;
+  int coef_kind = COEF_CONST;
+  double coef_value = 1.0;
+  DevBuf d_coef;                // [ne][q^3] when coef_kind == COEF_QPTS
+  DevBuf d_tab64, d_tab32;      // B[q][n], G[q][n], pts[q], wts[q]
+  DevBuf d_qd64, d_qd32;        // quadrature data
+  bool have64 = false, have32 = false;
+  int scatter_mode = PAFEM_SCATTER_ATOMIC;
+  DevBuf d_evec;                // E-vector workspace (deterministic scatter, diagonal, rhs)
+  DevBuf d_flag;                // int error flag for assembly
+  // solver workspace
+  DevBuf d_cg;                  // vectors
+  DevBuf d_part;                // reduction partials
+  DevBuf d_state;               // CgState
+  DevBuf d_dinv64, d_dinv32;
+  bool have_dinv = false;
+};
+
+// Shared host helpers (api.cpp).
+int ensure_et(Space* sp);
+template <typename T>
+int apply_impl(Op* op, const T* x, T* y, int constrained, const int* skip, hipStream_t s);
+int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (k_*.hip)
+// ---------------------------------------------------------------------------
+struct GeomArgs {
+  const double* verts;  // [(nx+1)(ny+1)(nz+1)][3]
+  int nx, ny, nz;
+  int64_t ne;
+  int q;
+  const double* pts;  // [q]
+  const double* wts;  // [q]
+};
+
+// Quadrature data (and optionally physical qpoint coordinates).
+hipError_t launch_qdata(const GeomArgs& g, int kind, int coef_kind, double coef_value,
+                        const double* coef_q, double* qd64, float* qd32, int* err_flag,
+                        hipStream_t s);
+hipError_t launch_qpoint_coords(const GeomArgs& g, double* xyz, hipStream_t s);
+
+template <typename T>
+struct ApplyArgs {
+  const T* x;
+  T* y;               // L-vector output (atomic mode)
+  T* yE;              // E-vector output (deterministic mode)
+  const int32_t* E;
+  const uint8_t* ess_mask;
+  const T* qd;
+  const T* B;         // [q][n]
+  const T* G;         // [q][n]
+  int64_t ne;
+  int constrained;
+  const int* skip;    // if non-null and *skip != 0, the kernel does nothing
+};
+
+// y (atomic) or yE (deterministic) from one fused sum-factorized element pass.
+template <typename T>
+hipError_t launch_apply(int kind, int p, int q, int scatter_mode, const ApplyArgs<T>& a,
+                        hipStream_t s);
+
+// Element-diagonal (E-vector) by sum factorization.
+hipError_t launch_diag_elem(int kind, int p, int q, const double* qd, const double* B,
+                            const double* G, int64_t ne, double* dE, hipStream_t s);
+// RHS element vectors b_e = B^T (w detJ f) with the geometry recomputed.
+hipError_t launch_rhs_elem(const GeomArgs& g, int p, const double* B, const double* f_q,
+                           double* bE, hipStream_t s);
+
+// Deterministic E^T: y[i] = sum over E^T row i of yE (fixed order); constrained
+// rows take x[i] (or 0 when x == nullptr).  If pdot != nullptr also writes
+// per-block partials of sum_i y[i]*w[i] (w = dot_with) for a fused dot.
+template <typename T>
+hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
+                            const uint8_t* ess_mask, int constrained, const T* x, T* y,
+                            int64_t ndofs, const int* skip, hipStream_t s);
+
+// Essential-dof fix-up: y[ess[i]] = x ? x[ess[i]] : value.
+template <typename T>
+hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, T* y,
+                          const int* skip, hipStream_t s);
+// y[0..n) = value (a kernel, so it may be recorded in a graph).
+template <typename T>
+hipError_t launch_fill(T* y, int64_t n, T value, const int* skip, hipStream_t s);
+
+// Reductions: fixed grid, per-block partials, then one-block fixed-order finish.
+int reduce_blocks(int64_t n);
+template <typename T>
+hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partials, int nb,
+                              const int* skip, hipStream_t s);
+hipError_t launch_sum_final(const double* partials, int nb, int ncols, double* out,
+                            hipStream_t s);
+
+// CG building blocks.
+template <typename T>
+hipError_t launch_cg_init(const T* r, const T* dinv, T* p, int64_t n, double* partials, int nb,
+                          hipStream_t s);
+hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
+                                int maxit, CgState* st, hipStream_t s);
+hipError_t launch_cg_alpha(const double* partials, int nb, CgState* st, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_update(T* x, T* r, const T* p, const T* Ap, const T* dinv, int64_t n,
+                            double* partials, int nb, const CgState* st, hipStream_t s);
+hipError_t launch_cg_beta(const double* partials, int nb, CgState* st, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_pupdate(T* p, const T* r, const T* dinv, int64_t n, const CgState* st,
+                             hipStream_t s);
+
+// Mixed-precision helpers.
+hipError_t launch_residual(const double* b, const double* Ax, double* r, int64_t n,
+                           hipStream_t s);
+hipError_t launch_scale_to_f32(const double* r, const double* norm2, float* r32, int64_t n,
+                               hipStream_t s);
+hipError_t launch_axpy_from_f32(double* x, const double* norm2, const float* d32, int64_t n,
+                                hipStream_t s);
+hipError_t launch_recip(const double* d, double* dinv64, float* dinv32, int64_t n,
+                        hipStream_t s);
+
+}  // namespace pafem

@@ -1,0 +1,425 @@
+// Vector kernels of the Jacobi-PCG solve, the deterministic E^T gather and
+// fixed-order reductions.
+//
+// Reductions are two-stage and bitwise reproducible for a given length: a
+// fixed grid of `reduce_blocks(n)` workgroups each folds a grid-stride slice,
+// reduces across the 64-lane wavefront with cross-lane shuffles and across the
+// workgroup's wavefronts through LDS, and writes one partial; a one-workgroup
+// kernel then sums the partials in a fixed tree order.  CG scalars (alpha,
+// beta, residual norms) never leave the device.
+#include "internal.h"
+
+namespace pafem {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWave = 64;
+constexpr int kMaxBlocks = 2048;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the workgroup of NV values per thread; results valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV]) {
+  __shared__ double s[NV][kThreads / kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double w = wave_sum(v[k]);
+    if (lane == 0) s[k][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double acc = 0;
+      for (int i = 0; i < kThreads / kWave; ++i) acc += s[k][i];
+      out[k] = acc;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE,
+                                                        const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ idx,
+                                                        const uint8_t* __restrict__ ess_mask,
+                                                        int constrained, const T* __restrict__ x,
+                                                        T* __restrict__ y, int64_t n,
+                                                        const int* skip) {
+  if (skip != nullptr && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (constrained && ess_mask[i]) {
+    y[i] = x ? x[i] : T(0);
+    return;
+  }
+  T acc = 0;
+  const int32_t b = off[i], en = off[i + 1];
+  for (int32_t k = b; k < en; ++k) acc += yE[idx[k]];
+  y[i] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_set_ess(const int32_t* __restrict__ ess, int64_t n,
+                                                      const T* __restrict__ x, T value,
+                                                      T* __restrict__ y, const int* skip) {
+  if (skip != nullptr && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t g = ess[i];
+  y[g] = x ? x[g] : value;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill(T* __restrict__ y, int64_t n, T value,
+                                                   const int* skip) {
+  if (skip != nullptr && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    y[i] = value;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot_partial(const T* __restrict__ x,
+                                                          const T* __restrict__ y, int64_t n,
+                                                          double* __restrict__ partials,
+                                                          const int* skip) {
+  if (skip != nullptr && *skip) return;
+  double v[1] = {0.0}, out[1];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    v[0] += (double)x[i] * (double)y[i];
+  block_sum<1>(v, out);
+  if (threadIdx.x == 0) partials[blockIdx.x] = out[0];
+}
+
+// Sum `ncols` interleaved columns of partials[nb][ncols] in fixed order.
+__device__ __forceinline__ void final_sums(const double* partials, int nb, int ncols,
+                                           double* out) {
+  __shared__ double s[4][kThreads];
+  for (int c = 0; c < ncols; ++c) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) acc += partials[i * ncols + c];
+    s[c][threadIdx.x] = acc;
+  }
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < ncols; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < ncols; ++c) out[c] = s[c][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_final(const double* __restrict__ partials,
+                                                        int nb, int ncols,
+                                                        double* __restrict__ out) {
+  double r[4];
+  final_sums(partials, nb, ncols, r);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < ncols; ++c) out[c] = r[c];
+}
+
+// ---- CG ------------------------------------------------------------------------
+
+// p = dinv .* r; partials of (r . p, r . r)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_init(const T* __restrict__ r,
+                                                      const T* __restrict__ dinv,
+                                                      T* __restrict__ p, int64_t n,
+                                                      double* __restrict__ partials) {
+  double v[2] = {0.0, 0.0}, out[2];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const T ri = r[i];
+    const T zi = dinv[i] * ri;
+    p[i] = zi;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_sum<2>(v, out);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = out[0];
+    partials[2 * blockIdx.x + 1] = out[1];
+  }
+}
+
+__global__ void k_cg_init_final(const double* __restrict__ partials, int nb, double bb,
+                                double rtol, int maxit, CgState* st) {
+  double r[4];
+  final_sums(partials, nb, 2, r);
+  if (threadIdx.x == 0) {
+    st->rz = r[0];
+    st->rr = r[1];
+    st->bb = bb;
+    st->rr_stop = rtol * rtol * bb;
+    st->pAp = st->alpha = st->beta = 0.0;
+    st->iter = 0;
+    st->maxit = maxit;
+    st->done = (r[1] <= st->rr_stop) || maxit <= 0;
+  }
+}
+
+__global__ void k_cg_alpha(const double* __restrict__ partials, int nb, CgState* st) {
+  if (st->done) return;
+  double r[4];
+  final_sums(partials, nb, 1, r);
+  if (threadIdx.x == 0) {
+    st->pAp = r[0];
+    st->alpha = st->rz / r[0];
+  }
+}
+
+// x += alpha p; r -= alpha Ap; partials of (r . z, r . r) with z = dinv .* r
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p,
+                                                        const T* __restrict__ Ap,
+                                                        const T* __restrict__ dinv, int64_t n,
+                                                        double* __restrict__ partials,
+                                                        const CgState* __restrict__ st) {
+  if (st->done) return;
+  const T alpha = (T)st->alpha;
+  double v[2] = {0.0, 0.0}, out[2];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_sum<2>(v, out);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = out[0];
+    partials[2 * blockIdx.x + 1] = out[1];
+  }
+}
+
+__global__ void k_cg_beta(const double* __restrict__ partials, int nb, CgState* st) {
+  if (st->done) return;
+  double r[4];
+  final_sums(partials, nb, 2, r);
+  if (threadIdx.x == 0) {
+    st->beta = r[0] / st->rz;
+    st->rz = r[0];
+    st->rr = r[1];
+    st->iter += 1;
+    if (r[1] <= st->rr_stop || st->iter >= st->maxit) st->done = 1;
+  }
+}
+
+// p = dinv .* r + beta p
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_pupdate(T* __restrict__ p,
+                                                         const T* __restrict__ r,
+                                                         const T* __restrict__ dinv, int64_t n,
+                                                         const CgState* __restrict__ st) {
+  if (st->done) return;
+  const T beta = (T)st->beta;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    p[i] = dinv[i] * r[i] + beta * p[i];
+}
+
+// ---- mixed precision ------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_residual(const double* __restrict__ b,
+                                                       const double* __restrict__ Ax,
+                                                       double* __restrict__ r, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    r[i] = b[i] - Ax[i];
+}
+
+// r32 = r / ||r||  (norm2 holds ||r||^2)
+__global__ __launch_bounds__(kThreads) void k_scale_to_f32(const double* __restrict__ r,
+                                                           const double* __restrict__ norm2,
+                                                           float* __restrict__ r32, int64_t n) {
+  const double nr = sqrt(*norm2);
+  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    r32[i] = (float)(r[i] * inv);
+}
+
+// x += ||r|| d32
+__global__ __launch_bounds__(kThreads) void k_axpy_from_f32(double* __restrict__ x,
+                                                            const double* __restrict__ norm2,
+                                                            const float* __restrict__ d32,
+                                                            int64_t n) {
+  const double nr = sqrt(*norm2);
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    x[i] += nr * (double)d32[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_recip(const double* __restrict__ d,
+                                                    double* __restrict__ dinv64,
+                                                    float* __restrict__ dinv32, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double v = 1.0 / d[i];
+    if (dinv64) dinv64[i] = v;
+    if (dinv32) dinv32[i] = (float)v;
+  }
+}
+
+inline int grid_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int reduce_blocks(int64_t n) {
+  int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T>
+hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
+                            const uint8_t* ess_mask, int constrained, const T* x, T* y,
+                            int64_t ndofs, const int* skip, hipStream_t s) {
+  if (ndofs == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather_et<T>), dim3((ndofs + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     s, yE, off, idx, ess_mask, constrained, x, y, ndofs, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_gather_et<double>(const double*, const int32_t*, const int32_t*,
+                                             const uint8_t*, int, const double*, double*, int64_t,
+                                             const int*, hipStream_t);
+template hipError_t launch_gather_et<float>(const float*, const int32_t*, const int32_t*,
+                                            const uint8_t*, int, const float*, float*, int64_t,
+                                            const int*, hipStream_t);
+
+template <typename T>
+hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, T* y,
+                          const int* skip, hipStream_t s) {
+  if (n_ess == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_set_ess<T>), dim3((n_ess + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     ess, n_ess, x, value, y, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_set_ess<double>(const int32_t*, int64_t, const double*, double, double*,
+                                           const int*, hipStream_t);
+template hipError_t launch_set_ess<float>(const int32_t*, int64_t, const float*, float, float*,
+                                          const int*, hipStream_t);
+
+template <typename T>
+hipError_t launch_fill(T* y, int64_t n, T value, const int* skip, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, n, value, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double*, int64_t, double, const int*, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, const int*, hipStream_t);
+
+template <typename T>
+hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partials, int nb,
+                              const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot_partial<T>), dim3(nb), dim3(kThreads), 0, s, x, y, n, partials, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_dot_partial<double>(const double*, const double*, int64_t, double*, int,
+                                               const int*, hipStream_t);
+template hipError_t launch_dot_partial<float>(const float*, const float*, int64_t, double*, int,
+                                              const int*, hipStream_t);
+
+hipError_t launch_sum_final(const double* partials, int nb, int ncols, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kThreads), 0, s, partials, nb, ncols, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_init(const T* r, const T* dinv, T* p, int64_t n, double* partials, int nb,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_init<T>), dim3(nb), dim3(kThreads), 0, s, r, dinv, p, n, partials);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_init<double>(const double*, const double*, double*, int64_t,
+                                           double*, int, hipStream_t);
+template hipError_t launch_cg_init<float>(const float*, const float*, float*, int64_t, double*,
+                                          int, hipStream_t);
+
+hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
+                                int maxit, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kThreads), 0, s, partials, nb, bb, rtol,
+                     maxit, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(const double* partials, int nb, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kThreads), 0, s, partials, nb, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update(T* x, T* r, const T* p, const T* Ap, const T* dinv, int64_t n,
+                            double* partials, int nb, const CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<T>), dim3(nb), dim3(kThreads), 0, s, x, r, p, Ap, dinv, n,
+                     partials, st);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_update<double>(double*, double*, const double*, const double*,
+                                             const double*, int64_t, double*, int,
+                                             const CgState*, hipStream_t);
+template hipError_t launch_cg_update<float>(float*, float*, const float*, const float*,
+                                            const float*, int64_t, double*, int, const CgState*,
+                                            hipStream_t);
+
+hipError_t launch_cg_beta(const double* partials, int nb, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kThreads), 0, s, partials, nb, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_pupdate(T* p, const T* r, const T* dinv, int64_t n, const CgState* st,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_pupdate<T>), dim3(grid_for(n)), dim3(kThreads), 0, s, p, r, dinv, n,
+                     st);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_pupdate<double>(double*, const double*, const double*, int64_t,
+                                              const CgState*, hipStream_t);
+template hipError_t launch_cg_pupdate<float>(float*, const float*, const float*, int64_t,
+                                             const CgState*, hipStream_t);
+
+hipError_t launch_residual(const double* b, const double* Ax, double* r, int64_t n,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(kThreads), 0, s, b, Ax, r, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f32(const double* r, const double* norm2, float* r32, int64_t n,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_to_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, r, norm2, r32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_from_f32(double* x, const double* norm2, const float* d32, int64_t n,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_from_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, x, norm2, d32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_recip(const double* d, double* dinv64, float* dinv32, int64_t n,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_recip, dim3(grid_for(n)), dim3(kThreads), 0, s, d, dinv64, dinv32, n);
+  return hipGetLastError();
+}
+
+}  // namespace pafem

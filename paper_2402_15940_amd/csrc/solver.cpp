@@ -1,0 +1,232 @@
+// Jacobi-preconditioned conjugate gradient on the partially assembled
+// operator, and FP64 defect correction around an FP32 inner PCG.
+//
+// All CG scalars live in a device-resident CgState; one iteration is six
+// kernels (apply, p.Ap partial dot, alpha, update + (r.z, r.r) partials,
+// beta, direction update) with no host round trip.  The host reads the state
+// every `check_every` iterations; kernels of iterations enqueued after
+// convergence see state.done and return at once.
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace pafem {
+
+namespace {
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+struct CgResult {
+  int iterations = 0;
+  double rr = 0.0, bb = 0.0;
+  bool converged = false;
+};
+
+// Solve A x = rhs for the constrained operator in precision T.  On entry x is
+// the initial guess unless x0_zero.  r, p, Ap are work vectors of length n.
+template <typename T>
+int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T* dinv,
+            double rtol, int maxit, int check_every, hipStream_t s, CgResult& res) {
+  Space* sp = op->space;
+  const int64_t n = sp->ndofs;
+  const int nb = reduce_blocks(n);
+  PAFEM_TRY(op->d_part.ensure((size_t)nb * 2 * sizeof(double) + 8 * sizeof(double)));
+  PAFEM_TRY(op->d_state.ensure(sizeof(CgState)));
+  double* part = op->d_part.as<double>();
+  double* bbdev = part + 2 * nb;
+  CgState* st = op->d_state.as<CgState>();
+
+  // b.b for the stopping test
+  PAFEM_TRY_HIP(launch_dot_partial<T>(rhs, rhs, n, part, nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, bbdev, s));
+  double bb = 0.0;
+  PAFEM_TRY_HIP(hipMemcpyAsync(&bb, bbdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
+  res.bb = bb;
+
+  // r = rhs - A x
+  if (x0_zero) {
+    PAFEM_TRY_HIP(launch_fill<T>(x, n, T(0), nullptr, s));
+    if (r != rhs)
+      PAFEM_TRY_HIP(hipMemcpyAsync(r, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  } else {
+    PAFEM_TRY(apply_impl<T>(op, x, Ap, 1, nullptr, s));
+    if (std::is_same<T, double>::value) {
+      PAFEM_TRY_HIP(launch_residual((const double*)rhs, (const double*)Ap, (double*)r, n, s));
+    } else {
+      set_error("internal: FP32 PCG needs a zero initial guess");
+      return PAFEM_ERR_INVALID_ARG;
+    }
+  }
+  PAFEM_TRY_HIP(launch_cg_init<T>(r, dinv, p, n, part, nb, s));
+  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, bb, rtol, maxit, st, s));
+
+  const int* done = &st->done;
+  CgState hs{};
+  for (;;) {
+    for (int k = 0; k < check_every; ++k) {
+      PAFEM_TRY(apply_impl<T>(op, p, Ap, 1, done, s));
+      PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
+      PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
+      PAFEM_TRY_HIP(launch_cg_update<T>(x, r, p, Ap, dinv, n, part, nb, st, s));
+      PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+      PAFEM_TRY_HIP(launch_cg_pupdate<T>(p, r, dinv, n, st, s));
+    }
+    PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    PAFEM_TRY_HIP(hipStreamSynchronize(s));
+    if (hs.done) break;
+  }
+  res.iterations = hs.iter;
+  res.rr = hs.rr;
+  res.converged = hs.rr <= hs.rr_stop;
+  return PAFEM_OK;
+}
+
+int ensure_dinv(Op* op, hipStream_t s, bool want32) {
+  Space* sp = op->space;
+  const int64_t n = sp->ndofs;
+  if (!op->have_dinv || (want32 && !op->d_dinv32.ptr)) {
+    PAFEM_TRY(op->d_dinv64.ensure(n * sizeof(double)));
+    PAFEM_TRY(op->d_dinv32.ensure(n * sizeof(float)));
+    double* d = op->d_dinv64.as<double>();
+    PAFEM_TRY(diagonal_impl(op, d, 1, s));
+    PAFEM_TRY_HIP(launch_set_ess<double>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), nullptr,
+                                         1.0, d, nullptr, s));
+    PAFEM_TRY_HIP(launch_recip(d, d, op->d_dinv32.as<float>(), n, s));
+    op->have_dinv = true;
+  }
+  return PAFEM_OK;
+}
+
+// ||b - A x|| / ||b|| in FP64 (uses the vectors r and Ax as scratch).
+int true_residual(Op* op, const double* b, const double* x, double* Ax, double* r, double bb,
+                  hipStream_t s, double& out) {
+  const int64_t n = op->space->ndofs;
+  const int nb = reduce_blocks(n);
+  double* part = op->d_part.as<double>();
+  double* dev = part + 2 * nb + 1;
+  PAFEM_TRY(apply_impl<double>(op, x, Ax, 1, nullptr, s));
+  PAFEM_TRY_HIP(launch_residual(b, Ax, r, n, s));
+  PAFEM_TRY_HIP(launch_dot_partial<double>(r, r, n, part, nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, dev, s));
+  double rr = 0.0;
+  PAFEM_TRY_HIP(hipMemcpyAsync(&rr, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
+  out = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+  return PAFEM_OK;
+}
+
+}  // namespace
+
+}  // namespace pafem
+
+using namespace pafem;
+
+extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
+                              const pafem_solve_opts* o, pafem_solve_stats* stats,
+                              void* stream) {
+  clear_error();
+  Op* op = reinterpret_cast<Op*>(op_);
+  if (!op || !b || !x || !o || !stats) {
+    set_error("NULL argument");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  if (!(o->rtol > 0.0) || o->maxit < 1 || o->check_every < 1) {
+    set_error("need rtol > 0, maxit >= 1, check_every >= 1");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  if (o->mode != PAFEM_SOLVE_PLAIN_FP64 && o->mode != PAFEM_SOLVE_IR_FP32) {
+    set_error("unknown solve mode");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  if (!op->have64 || (o->mode == PAFEM_SOLVE_IR_FP32 && !op->have32)) {
+    set_error("operator not assembled in the precision the mode needs");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  if (op->space->mesh->ctx->host_only) {
+    set_error("solve needs a GPU context");
+    return PAFEM_ERR_UNSUPPORTED;
+  }
+  PAFEM_TRY_HIP(hipSetDevice(op->space->mesh->ctx->device));
+  hipStream_t s = S(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  Space* sp = op->space;
+  const int64_t n = sp->ndofs;
+  *stats = pafem_solve_stats{};
+
+  PAFEM_TRY(ensure_dinv(op, s, o->mode == PAFEM_SOLVE_IR_FP32));
+  // workspace: 3 FP64 vectors, plus 4 FP32 vectors for IR
+  const size_t need = 3 * n * sizeof(double) + (o->mode == PAFEM_SOLVE_IR_FP32 ? 4 * n * sizeof(float) : 0);
+  PAFEM_TRY(op->d_cg.ensure(need));
+  double* r = op->d_cg.as<double>();
+  double* p = r + n;
+  double* Ap = p + n;
+
+  int rc = PAFEM_OK;
+  if (o->mode == PAFEM_SOLVE_PLAIN_FP64) {
+    CgResult res;
+    PAFEM_TRY(run_pcg<double>(op, b, x, false, r, p, Ap, op->d_dinv64.as<double>(), o->rtol,
+                              o->maxit, o->check_every, s, res));
+    stats->iterations = res.iterations;
+    stats->rel_res = res.bb > 0 ? std::sqrt(res.rr / res.bb) : 0.0;
+    PAFEM_TRY(true_residual(op, b, x, Ap, r, res.bb, s, stats->true_rel_res));
+    if (!res.converged) rc = PAFEM_ERR_NOT_CONVERGED;
+  } else {
+    float* d32 = reinterpret_cast<float*>(Ap + n);
+    float* r32 = d32 + n;
+    float* p32 = r32 + n;
+    float* Ap32 = p32 + n;
+    const int nb = reduce_blocks(n);
+    PAFEM_TRY(op->d_part.ensure((size_t)nb * 2 * sizeof(double) + 8 * sizeof(double)));
+    double* part = op->d_part.as<double>();
+    double* rr_dev = part + 2 * nb + 2;  // ||r||^2 of the current outer residual
+    // bb
+    PAFEM_TRY_HIP(launch_dot_partial<double>(b, b, n, part, nb, nullptr, s));
+    PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, rr_dev, s));
+    double bb = 0.0;
+    PAFEM_TRY_HIP(hipMemcpyAsync(&bb, rr_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    PAFEM_TRY_HIP(hipStreamSynchronize(s));
+    // r = b - A x (FP64)
+    PAFEM_TRY(apply_impl<double>(op, x, Ap, 1, nullptr, s));
+    PAFEM_TRY_HIP(launch_residual(b, Ap, r, n, s));
+    int total_inner = 0, outer = 0;
+    double rel = 0.0;
+    bool ok = false;
+    for (;;) {
+      PAFEM_TRY_HIP(launch_dot_partial<double>(r, r, n, part, nb, nullptr, s));
+      PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, rr_dev, s));
+      double rr = 0.0;
+      PAFEM_TRY_HIP(hipMemcpyAsync(&rr, rr_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+      PAFEM_TRY_HIP(hipStreamSynchronize(s));
+      rel = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+      if (rel <= o->rtol) {
+        ok = true;
+        break;
+      }
+      if (outer >= o->max_outer) break;
+      // inner FP32 solve of A d = r / ||r||
+      PAFEM_TRY_HIP(launch_scale_to_f32(r, rr_dev, r32, n, s));
+      CgResult res;
+      // the inner solve overwrites the partials; keep ||r||^2 in its own slot
+      PAFEM_TRY(run_pcg<float>(op, r32, d32, true, r32, p32, Ap32, op->d_dinv32.as<float>(),
+                               o->inner_rtol > 0 ? o->inner_rtol : 1e-4, o->maxit,
+                               o->check_every, s, res));
+      total_inner += res.iterations;
+      PAFEM_TRY_HIP(launch_axpy_from_f32(x, rr_dev, d32, n, s));
+      PAFEM_TRY(apply_impl<double>(op, x, Ap, 1, nullptr, s));
+      PAFEM_TRY_HIP(launch_residual(b, Ap, r, n, s));
+      ++outer;
+    }
+    stats->iterations = total_inner;
+    stats->outer_iterations = outer;
+    stats->rel_res = rel;
+    stats->true_rel_res = rel;
+    if (!ok) rc = PAFEM_ERR_NOT_CONVERGED;
+  }
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
+  stats->seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rc == PAFEM_ERR_NOT_CONVERGED) set_error("iteration limit reached before rtol");
+  return rc;
+}
