@@ -28,9 +28,9 @@
  * Conventions
  *   - Every call returns int: PAFEM_OK (0) or a negative PAFEM_ERR_* code;
  *     pafem_last_error() then holds a message (per calling thread).
- *   - Handles are opaque, owned by the library, released by *_destroy.  A
- *     space keeps its mesh alive and an operator its space: destroy in reverse
- *     order of creation (children first).
+ *   - Handles are opaque, owned by the library, released by *_destroy.  Objects
+ *     are reference counted: a mesh keeps its context alive, a space its mesh
+ *     and an operator its space, so handles may be destroyed in any order.
  *   - Vectors passed as "_dev" are device pointers owned by the caller,
  *     contiguous, of the element type stated; the library never frees them.
  *     "_host" pointers are host memory, copied before the call returns.

@@ -138,6 +138,44 @@ struct pafem_mesh : Mesh {};
 struct pafem_space : Space {};
 struct pafem_op : Op {};
 
+namespace {
+
+void release(pafem_ctx* c) {
+  if (c && --c->refs == 0) {
+    if (!c->host_only) (void)hipSetDevice(c->device);
+    delete c;
+  }
+}
+
+void release(pafem_mesh* m) {
+  if (m && --m->refs == 0) {
+    auto* c = static_cast<pafem_ctx*>(m->ctx);
+    if (!c->host_only) (void)hipSetDevice(c->device);
+    delete m;
+    release(c);
+  }
+}
+
+void release(pafem_space* s) {
+  if (s && --s->refs == 0) {
+    auto* m = static_cast<pafem_mesh*>(s->mesh);
+    if (!m->ctx->host_only) (void)hipSetDevice(m->ctx->device);
+    delete s;
+    release(m);
+  }
+}
+
+void release(pafem_op* o) {
+  if (o && --o->refs == 0) {
+    auto* s = static_cast<pafem_space*>(o->space);
+    (void)hipSetDevice(s->mesh->ctx->device);
+    delete o;
+    release(s);
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pafem_last_error(void) { return g_err.c_str(); }
@@ -173,10 +211,7 @@ int pafem_ctx_create(int device, pafem_ctx** out) {
 }
 
 int pafem_ctx_destroy(pafem_ctx* ctx) {
-  if (ctx) {
-    if (!ctx->host_only) (void)hipSetDevice(ctx->device);
-    delete ctx;
-  }
+  release(ctx);
   return PAFEM_OK;
 }
 
@@ -204,12 +239,13 @@ int pafem_mesh_create_structured(pafem_ctx* ctx, int nx, int ny, int nz,
       return rc;
     }
   }
+  ++ctx->refs;
   *out = m;
   return PAFEM_OK;
 }
 
 int pafem_mesh_destroy(pafem_mesh* mesh) {
-  delete mesh;
+  release(mesh);
   return PAFEM_OK;
 }
 
@@ -243,12 +279,13 @@ int pafem_space_create(pafem_mesh* mesh, int p, pafem_space** out) {
       return rc;
     }
   }
+  ++mesh->refs;
   *out = sp;
   return PAFEM_OK;
 }
 
 int pafem_space_destroy(pafem_space* space) {
-  delete space;
+  release(space);
   return PAFEM_OK;
 }
 
@@ -328,15 +365,13 @@ int pafem_op_create(pafem_space* space, int kind, int q1d, pafem_op** out) {
     delete op;
     return rc;
   }
+  ++space->refs;
   *out = op;
   return PAFEM_OK;
 }
 
 int pafem_op_destroy(pafem_op* op) {
-  if (op) {
-    (void)hipSetDevice(op->space->mesh->ctx->device);
-    delete op;
-  }
+  release(op);
   return PAFEM_OK;
 }
 

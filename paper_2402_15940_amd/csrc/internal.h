@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -89,20 +90,27 @@ void build_essential(int nx, int ny, int nz, int p, std::vector<int32_t>& ess,
 // ---------------------------------------------------------------------------
 // library objects
 // ---------------------------------------------------------------------------
-struct Ctx {
+// Library objects are reference counted: the caller's handle holds one
+// reference and every child (mesh of a context, space of a mesh, operator of a
+// space) holds one on its parent, so handles may be destroyed in any order.
+struct RefCounted {
+  std::atomic<int> refs{1};
+};
+
+struct Ctx : RefCounted {
   int device = -1;
   bool host_only = true;
   DevBuf scratch;  // reduction partials for pafem_dot
 };
 
-struct Mesh {
+struct Mesh : RefCounted {
   Ctx* ctx = nullptr;
   int nx = 0, ny = 0, nz = 0;
   std::vector<double> verts;
   DevBuf d_verts;
 };
 
-struct Space {
+struct Space : RefCounted {
   Mesh* mesh = nullptr;
   int p = 0;
   int64_t ndofs = 0, ne = 0;
@@ -128,7 +136,7 @@ struct CgState {
   int pad;
 };
 
-struct Op {
+struct Op : RefCounted {
   Space* space = nullptr;
   int kind = PAFEM_DIFFUSION;
   int q = 0;

@@ -87,3 +87,16 @@ def test_errors_are_reported():
         pafem.Mesh(ctx, 2, 2, 2, bad)
     with pytest.raises(pafem.PafemError):
         pafem.basis_tables(3, 13)
+
+
+def test_handles_destroyed_in_any_order():
+    from paper_2402_15940_amd.pafem import lib
+    ctx = pafem.Context(-1)
+    mesh = pafem.Mesh(ctx, 2, 1, 1, inputs.perturbed_vertices(2, 1, 1, seed=None))
+    sp = pafem.Space(mesh, 3)
+    ctx.close()
+    mesh.close()
+    # the space still holds its mesh and context
+    assert sp.ndofs == 7 * 4 * 4
+    np.testing.assert_array_equal(sp.restriction(), fem.element_restriction(2, 1, 1, 3))
+    sp.close()
