@@ -205,7 +205,7 @@ int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem
 
 /* ---- reductions (exposed for testing the CG building blocks) --------------------- */
 /* result_dev[0] = sum_i x[i] y[i] over n doubles, fixed-order two-stage
- * reduction (bitwise reproducible for a given n). */
+ * reduction (bitwise reproducible for a given n); x, y may be NULL when n = 0. */
 int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x_dev, const double* y_dev,
               double* result_dev, void* stream);
 

@@ -533,7 +533,7 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_q, double* b, void* stream)
 int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x, const double* y, double* result,
               void* stream) {
   clear_error();
-  CHECK_ARG(ctx && x && y && result, "NULL argument");
+  CHECK_ARG(ctx && result && (n == 0 || (x && y)), "NULL argument");
   CHECK_ARG(n >= 0, "n must be >= 0");
   PAFEM_TRY(need_device(ctx));
   const int nb = reduce_blocks(n);
