@@ -69,6 +69,9 @@ extern "C" {
 #define PAFEM_SCATTER_ATOMIC 0        /* E^T by FP64/FP32 atomic adds (fast, run-to-run rounding differences) */
 #define PAFEM_SCATTER_DETERMINISTIC 1 /* E^T by E-vector + per-dof ordered sum (bitwise reproducible) */
 
+#define PAFEM_APPLY_CONSTRAINED 1 /* flag: identity rows/columns on essential dofs */
+#define PAFEM_APPLY_ACCUMULATE 2  /* flag: y += A x instead of y = A x */
+
 #define PAFEM_SOLVE_PLAIN_FP64 0 /* Jacobi-PCG entirely in FP64 */
 #define PAFEM_SOLVE_IR_FP32 1    /* FP64 defect correction around an FP32 Jacobi-PCG */
 
@@ -159,11 +162,13 @@ int pafem_op_get_qdata(pafem_op* op, int prec, void* dst_dev, void* stream);
 int pafem_op_set_scatter_mode(pafem_op* op, int mode);
 
 /* y = A x.  prec selects double (PAFEM_FP64) or float (PAFEM_FP32, needs the
- * FP32 copy) vectors of length ndofs; x and y must not alias.
- * constrained = 0: the plain assembled operator.  constrained = 1: rows and
- * columns of essential dofs replaced by the identity (y_ess = x_ess, free rows
- * see x with essential entries zeroed). */
-int pafem_op_apply(pafem_op* op, int prec, const void* x_dev, void* y_dev, int constrained,
+ * FP32 copy) vectors of length ndofs; x and y must not alias.  flags:
+ *   0: the plain assembled operator;
+ *   PAFEM_APPLY_CONSTRAINED: rows and columns of essential dofs replaced by
+ *     the identity (y_ess = x_ess, free rows see x with essential entries 0);
+ *   PAFEM_APPLY_ACCUMULATE: add the result to y instead of overwriting it (in
+ *     the default atomic E^T mode this launches the element kernel alone). */
+int pafem_op_apply(pafem_op* op, int prec, const void* x_dev, void* y_dev, int flags,
                    void* stream);
 /* d = diag(A) by sum factorization (double, ndofs); constrained = 1 puts 1 on
  * essential dofs.  Bitwise reproducible. */

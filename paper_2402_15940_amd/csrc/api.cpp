@@ -77,9 +77,11 @@ int ensure_et(Space* sp) {
 }
 
 template <typename T>
-int apply_impl(Op* op, const T* x, T* y, int constrained, const int* skip, hipStream_t s) {
+int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s) {
   Space* sp = op->space;
   const int n = sp->p + 1;
+  const int constrained = (flags & PAFEM_APPLY_CONSTRAINED) ? 1 : 0;
+  const int accumulate = (flags & PAFEM_APPLY_ACCUMULATE) ? 1 : 0;
   const DevBuf& tab = std::is_same<T, double>::value ? op->d_tab64 : op->d_tab32;
   ApplyArgs<T> a;
   a.x = x;
@@ -99,13 +101,14 @@ int apply_impl(Op* op, const T* x, T* y, int constrained, const int* skip, hipSt
     a.yE = op->d_evec.as<T>();
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, a, s));
     PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(), sp->d_et_idx.as<int32_t>(),
-                                      a.ess_mask, constrained, x, y, sp->ndofs, skip, s));
+                                      a.ess_mask, constrained, accumulate, x, y, sp->ndofs, skip,
+                                      s));
   } else {
     // zero y with a kernel (not a memset) so the sequence can sit in a captured graph
-    PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
+    if (!accumulate) PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
     if (constrained)
-      PAFEM_TRY_HIP(launch_set_ess<T>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), x, T(0), y,
-                                      skip, s));
+      PAFEM_TRY_HIP(launch_set_ess<T>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), x, T(0),
+                                      accumulate, y, skip, s));
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_ATOMIC, a, s));
   }
   return PAFEM_OK;
@@ -122,7 +125,7 @@ int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
   // constrained rows get 1 (x = nullptr means 0, so set them afterwards)
   PAFEM_TRY_HIP(launch_gather_et<double>(op->d_evec.as<double>(), sp->d_et_off.as<int32_t>(),
                                          sp->d_et_idx.as<int32_t>(), sp->d_ess_mask.as<uint8_t>(),
-                                         0, nullptr, d, sp->ndofs, nullptr, s));
+                                         0, 0, nullptr, d, sp->ndofs, nullptr, s));
   return PAFEM_OK;
 }
 
@@ -479,20 +482,20 @@ int pafem_op_set_scatter_mode(pafem_op* op, int mode) {
   return PAFEM_OK;
 }
 
-int pafem_op_apply(pafem_op* op, int prec, const void* x, void* y, int constrained,
-                   void* stream) {
+int pafem_op_apply(pafem_op* op, int prec, const void* x, void* y, int flags, void* stream) {
   clear_error();
   CHECK_ARG(op && x && y, "NULL argument");
   CHECK_ARG(x != y, "x and y must not alias");
-  CHECK_ARG(constrained == 0 || constrained == 1, "constrained must be 0 or 1");
+  CHECK_ARG((flags & ~(PAFEM_APPLY_CONSTRAINED | PAFEM_APPLY_ACCUMULATE)) == 0,
+            "unknown apply flags");
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   if (prec == PAFEM_FP64) {
     CHECK_ARG(op->have64, "operator not assembled");
-    return apply_impl<double>(op, (const double*)x, (double*)y, constrained, nullptr, S(stream));
+    return apply_impl<double>(op, (const double*)x, (double*)y, flags, nullptr, S(stream));
   }
   if (prec == PAFEM_FP32) {
     CHECK_ARG(op->have32, "FP32 quadrature data not assembled");
-    return apply_impl<float>(op, (const float*)x, (float*)y, constrained, nullptr, S(stream));
+    return apply_impl<float>(op, (const float*)x, (float*)y, flags, nullptr, S(stream));
   }
   set_error("prec must be PAFEM_FP64 or PAFEM_FP32");
   return PAFEM_ERR_INVALID_ARG;
@@ -508,8 +511,8 @@ int pafem_op_diagonal(pafem_op* op, double* d, int constrained, void* stream) {
   PAFEM_TRY(diagonal_impl(op, d, constrained, s));
   if (constrained)
     PAFEM_TRY_HIP(launch_set_ess<double>(op->space->d_ess.as<int32_t>(),
-                                         (int64_t)op->space->ess.size(), nullptr, 1.0, d, nullptr,
-                                         s));
+                                         (int64_t)op->space->ess.size(), nullptr, 1.0, 0, d,
+                                         nullptr, s));
   return PAFEM_OK;
 }
 
@@ -526,7 +529,7 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_q, double* b, void* stream)
   PAFEM_TRY_HIP(launch_rhs_elem(g, sp->p, tabB<double>(op->d_tab64), f_q, op->d_evec.as<double>(), s));
   PAFEM_TRY_HIP(launch_gather_et<double>(op->d_evec.as<double>(), sp->d_et_off.as<int32_t>(),
                                          sp->d_et_idx.as<int32_t>(), sp->d_ess_mask.as<uint8_t>(),
-                                         1, nullptr, b, sp->ndofs, nullptr, s));
+                                         1, 0, nullptr, b, sp->ndofs, nullptr, s));
   return PAFEM_OK;
 }
 

@@ -161,7 +161,7 @@ struct Op : RefCounted {
 // Shared host helpers (api.cpp).
 int ensure_et(Space* sp);
 template <typename T>
-int apply_impl(Op* op, const T* x, T* y, int constrained, const int* skip, hipStream_t s);
+int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s);
 int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -209,18 +209,17 @@ hipError_t launch_diag_elem(int kind, int p, int q, const double* qd, const doub
 hipError_t launch_rhs_elem(const GeomArgs& g, int p, const double* B, const double* f_q,
                            double* bE, hipStream_t s);
 
-// Deterministic E^T: y[i] = sum over E^T row i of yE (fixed order); constrained
-// rows take x[i] (or 0 when x == nullptr).  If pdot != nullptr also writes
-// per-block partials of sum_i y[i]*w[i] (w = dot_with) for a fused dot.
+// Deterministic E^T: y[i] (+)= sum over E^T row i of yE (fixed order);
+// constrained rows take x[i] (or 0 when x == nullptr) instead of the sum.
 template <typename T>
 hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
-                            const uint8_t* ess_mask, int constrained, const T* x, T* y,
-                            int64_t ndofs, const int* skip, hipStream_t s);
+                            const uint8_t* ess_mask, int constrained, int accumulate, const T* x,
+                            T* y, int64_t ndofs, const int* skip, hipStream_t s);
 
-// Essential-dof fix-up: y[ess[i]] = x ? x[ess[i]] : value.
+// Essential-dof fix-up: y[ess[i]] (+)= x ? x[ess[i]] : value.
 template <typename T>
-hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, T* y,
-                          const int* skip, hipStream_t s);
+hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, int accumulate,
+                          T* y, const int* skip, hipStream_t s);
 // y[0..n) = value (a kernel, so it may be recorded in a graph).
 template <typename T>
 hipError_t launch_fill(T* y, int64_t n, T value, const int* skip, hipStream_t s);

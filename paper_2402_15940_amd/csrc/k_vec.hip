@@ -49,31 +49,34 @@ __global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE
                                                         const int32_t* __restrict__ off,
                                                         const int32_t* __restrict__ idx,
                                                         const uint8_t* __restrict__ ess_mask,
-                                                        int constrained, const T* __restrict__ x,
+                                                        int constrained, int accumulate,
+                                                        const T* __restrict__ x,
                                                         T* __restrict__ y, int64_t n,
                                                         const int* skip) {
   if (skip != nullptr && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (constrained && ess_mask[i]) {
-    y[i] = x ? x[i] : T(0);
-    return;
-  }
   T acc = 0;
-  const int32_t b = off[i], en = off[i + 1];
-  for (int32_t k = b; k < en; ++k) acc += yE[idx[k]];
-  y[i] = acc;
+  if (constrained && ess_mask[i]) {
+    acc = x ? x[i] : T(0);
+  } else {
+    const int32_t b = off[i], en = off[i + 1];
+    for (int32_t k = b; k < en; ++k) acc += yE[idx[k]];
+  }
+  y[i] = accumulate ? y[i] + acc : acc;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_set_ess(const int32_t* __restrict__ ess, int64_t n,
                                                       const T* __restrict__ x, T value,
-                                                      T* __restrict__ y, const int* skip) {
+                                                      int accumulate, T* __restrict__ y,
+                                                      const int* skip) {
   if (skip != nullptr && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t g = ess[i];
-  y[g] = x ? x[g] : value;
+  const T v = x ? x[g] : value;
+  y[g] = accumulate ? y[g] + v : v;
 }
 
 template <typename T>
@@ -291,31 +294,31 @@ int reduce_blocks(int64_t n) {
 
 template <typename T>
 hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
-                            const uint8_t* ess_mask, int constrained, const T* x, T* y,
-                            int64_t ndofs, const int* skip, hipStream_t s) {
+                            const uint8_t* ess_mask, int constrained, int accumulate, const T* x,
+                            T* y, int64_t ndofs, const int* skip, hipStream_t s) {
   if (ndofs == 0) return hipSuccess;
   hipLaunchKernelGGL((k_gather_et<T>), dim3((ndofs + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     s, yE, off, idx, ess_mask, constrained, x, y, ndofs, skip);
+                     s, yE, off, idx, ess_mask, constrained, accumulate, x, y, ndofs, skip);
   return hipGetLastError();
 }
 template hipError_t launch_gather_et<double>(const double*, const int32_t*, const int32_t*,
-                                             const uint8_t*, int, const double*, double*, int64_t,
-                                             const int*, hipStream_t);
+                                             const uint8_t*, int, int, const double*, double*,
+                                             int64_t, const int*, hipStream_t);
 template hipError_t launch_gather_et<float>(const float*, const int32_t*, const int32_t*,
-                                            const uint8_t*, int, const float*, float*, int64_t,
-                                            const int*, hipStream_t);
+                                            const uint8_t*, int, int, const float*, float*,
+                                            int64_t, const int*, hipStream_t);
 
 template <typename T>
-hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, T* y,
-                          const int* skip, hipStream_t s) {
+hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, int accumulate,
+                          T* y, const int* skip, hipStream_t s) {
   if (n_ess == 0) return hipSuccess;
   hipLaunchKernelGGL((k_set_ess<T>), dim3((n_ess + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                     ess, n_ess, x, value, y, skip);
+                     ess, n_ess, x, value, accumulate, y, skip);
   return hipGetLastError();
 }
-template hipError_t launch_set_ess<double>(const int32_t*, int64_t, const double*, double, double*,
-                                           const int*, hipStream_t);
-template hipError_t launch_set_ess<float>(const int32_t*, int64_t, const float*, float, float*,
+template hipError_t launch_set_ess<double>(const int32_t*, int64_t, const double*, double, int,
+                                           double*, const int*, hipStream_t);
+template hipError_t launch_set_ess<float>(const int32_t*, int64_t, const float*, float, int, float*,
                                           const int*, hipStream_t);
 
 template <typename T>

@@ -51,7 +51,7 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
     if (r != rhs)
       PAFEM_TRY_HIP(hipMemcpyAsync(r, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, s));
   } else {
-    PAFEM_TRY(apply_impl<T>(op, x, Ap, 1, nullptr, s));
+    PAFEM_TRY(apply_impl<T>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));
     if (std::is_same<T, double>::value) {
       PAFEM_TRY_HIP(launch_residual((const double*)rhs, (const double*)Ap, (double*)r, n, s));
     } else {
@@ -66,7 +66,7 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
   CgState hs{};
   for (;;) {
     for (int k = 0; k < check_every; ++k) {
-      PAFEM_TRY(apply_impl<T>(op, p, Ap, 1, done, s));
+      PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s));
       PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
       PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
       PAFEM_TRY_HIP(launch_cg_update<T>(x, r, p, Ap, dinv, n, part, nb, st, s));
@@ -92,7 +92,7 @@ int ensure_dinv(Op* op, hipStream_t s, bool want32) {
     double* d = op->d_dinv64.as<double>();
     PAFEM_TRY(diagonal_impl(op, d, 1, s));
     PAFEM_TRY_HIP(launch_set_ess<double>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), nullptr,
-                                         1.0, d, nullptr, s));
+                                         1.0, 0, d, nullptr, s));
     PAFEM_TRY_HIP(launch_recip(d, d, op->d_dinv32.as<float>(), n, s));
     op->have_dinv = true;
   }
@@ -106,7 +106,7 @@ int true_residual(Op* op, const double* b, const double* x, double* Ax, double* 
   const int nb = reduce_blocks(n);
   double* part = op->d_part.as<double>();
   double* dev = part + 2 * nb + 1;
-  PAFEM_TRY(apply_impl<double>(op, x, Ax, 1, nullptr, s));
+  PAFEM_TRY(apply_impl<double>(op, x, Ax, PAFEM_APPLY_CONSTRAINED, nullptr, s));
   PAFEM_TRY_HIP(launch_residual(b, Ax, r, n, s));
   PAFEM_TRY_HIP(launch_dot_partial<double>(r, r, n, part, nb, nullptr, s));
   PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, dev, s));
@@ -188,7 +188,7 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     PAFEM_TRY_HIP(hipMemcpyAsync(&bb, rr_dev, sizeof(double), hipMemcpyDeviceToHost, s));
     PAFEM_TRY_HIP(hipStreamSynchronize(s));
     // r = b - A x (FP64)
-    PAFEM_TRY(apply_impl<double>(op, x, Ap, 1, nullptr, s));
+    PAFEM_TRY(apply_impl<double>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));
     PAFEM_TRY_HIP(launch_residual(b, Ap, r, n, s));
     int total_inner = 0, outer = 0;
     double rel = 0.0;
@@ -214,7 +214,7 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
                                o->check_every, s, res));
       total_inner += res.iterations;
       PAFEM_TRY_HIP(launch_axpy_from_f32(x, rr_dev, d32, n, s));
-      PAFEM_TRY(apply_impl<double>(op, x, Ap, 1, nullptr, s));
+      PAFEM_TRY(apply_impl<double>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));
       PAFEM_TRY_HIP(launch_residual(b, Ap, r, n, s));
       ++outer;
     }

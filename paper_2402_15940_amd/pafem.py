@@ -22,6 +22,8 @@ FP64 = 1
 FP32 = 2
 SCATTER_ATOMIC = 0
 SCATTER_DETERMINISTIC = 1
+APPLY_CONSTRAINED = 1
+APPLY_ACCUMULATE = 2
 SOLVE_PLAIN_FP64 = 0
 SOLVE_IR_FP32 = 1
 
@@ -329,14 +331,18 @@ class Operator:
     def set_scatter_mode(self, mode: int):
         _check(lib().pafem_op_set_scatter_mode(self._h, mode))
 
-    def apply(self, x, y=None, constrained: bool = False, stream=None):
+    def apply(self, x, y=None, constrained: bool = False, accumulate: bool = False,
+              stream=None):
         torch = self._torch()
         prec = FP64 if x.dtype == torch.float64 else FP32
         n = self.space.ndofs
         if y is None:
+            if accumulate:
+                raise ValueError("accumulate needs y")
             y = torch.empty_like(x)
+        flags = (APPLY_CONSTRAINED if constrained else 0) | (APPLY_ACCUMULATE if accumulate else 0)
         _check(lib().pafem_op_apply(self._h, prec, _dptr(x, x.dtype, n, "x"),
-                                    _dptr(y, x.dtype, n, "y"), int(constrained), _stream(stream)))
+                                    _dptr(y, x.dtype, n, "y"), flags, _stream(stream)))
         return y
 
     def diagonal(self, constrained: bool = False, out=None, stream=None):

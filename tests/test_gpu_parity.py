@@ -407,3 +407,23 @@ def _node_coords_fast(v, N, p):
                 w = (s if i else 1 - s) * (t if j else 1 - t) * (u if k else 1 - u)
                 out += w[..., None] * V[ez + k, ey + j, ex + i]
     return out.reshape(-1, 3)
+
+
+@pytest.mark.parametrize("kind", ["mass", "diffusion"])
+def test_apply_accumulate(pf, ctx, kind):
+    nx, ny, nz, p = 3, 2, 2, 3
+    seed = 44
+    A = _oracle_matrix(kind, nx, ny, nz, p, seed, None)
+    v, op = _build(pf, ctx, kind, nx, ny, nz, p, seed)
+    n = op.space.ndofs
+    x = inputs.random_vector(n, 1)
+    y0 = inputs.random_vector(n, 2)
+    ess = fem.essential_dofs(nx, ny, nz, p)
+    for mode in (pf.SCATTER_ATOMIC, pf.SCATTER_DETERMINISTIC):
+        op.set_scatter_mode(mode)
+        for constrained in (False, True):
+            y = torch.from_numpy(y0.copy()).cuda()
+            op.apply(torch.from_numpy(x).cuda(), y, constrained=constrained, accumulate=True)
+            Ax = fem.constrained_apply(A, x, ess) if constrained else A @ x
+            e2, einf = _relerr(y.cpu().numpy(), y0 + Ax)
+            assert e2 <= 1e-12 and einf <= 1e-12, (mode, constrained, e2)
