@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--scatter", choices=["atomic", "deterministic"], default="atomic")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="stop after the headline applies and the copy reference (profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -202,6 +204,27 @@ def main():
                 "flops_per_launch": apply_flops(ne, n, q, "diffusion"),
                 "fp64_tflops": round(apply_flops(ne, n, q, "diffusion") / (ms_k * 1e-3) / 1e12, 2)}
     log(f"element kernel {ms_k:.4f} ms -> {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM)")
+
+    # ---- plain device copy of known size: the attainable-bandwidth reference ---------
+    copy_bytes = 1 << 30
+    ca = torch.empty(copy_bytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * copy_bytes / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del ca, cb
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"device copy {copy_gbs:.0f} GB/s (read+write of 1 GiB)")
+    if args.copy_only:
+        return
 
     extra = {}
     # ---- other applies on the same mesh ---------------------------------------
