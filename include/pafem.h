@@ -69,6 +69,9 @@ extern "C" {
 #define PAFEM_SCATTER_ATOMIC 0        /* E^T by FP64/FP32 atomic adds (fast, run-to-run rounding differences) */
 #define PAFEM_SCATTER_DETERMINISTIC 1 /* E^T by E-vector + per-dof ordered sum (bitwise reproducible) */
 
+#define PAFEM_INDEX_LATTICE 0 /* E computed from the lattice numbering in the kernels */
+#define PAFEM_INDEX_MAP 1     /* E and E^T read from the stored int32 maps            */
+
 #define PAFEM_APPLY_CONSTRAINED 1 /* flag: identity rows/columns on essential dofs */
 #define PAFEM_APPLY_ACCUMULATE 2  /* flag: y += A x instead of y = A x */
 
@@ -160,6 +163,11 @@ int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask);
 int pafem_op_get_qdata(pafem_op* op, int prec, void* dst_dev, void* stream);
 /* Choose how E^T sums element contributions (default ATOMIC). */
 int pafem_op_set_scatter_mode(pafem_op* op, int mode);
+/* Choose where the kernels take E (and, in deterministic mode, E^T) from:
+ * PAFEM_INDEX_LATTICE (default) computes the lattice numbering in the kernel;
+ * PAFEM_INDEX_MAP reads the stored maps (the ones pafem_space_get_restriction*
+ * return).  Both give identical results. */
+int pafem_op_set_restriction_mode(pafem_op* op, int mode);
 
 /* y = A x.  prec selects double (PAFEM_FP64) or float (PAFEM_FP32, needs the
  * FP32 copy) vectors of length ndofs; x and y must not alias.  flags:

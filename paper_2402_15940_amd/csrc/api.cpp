@@ -93,23 +93,32 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   a.B = tabB<T>(tab);
   a.G = tabG<T>(tab, op->q, n);
   a.ne = sp->ne;
+  a.nx = sp->mesh->nx;
+  a.ny = sp->mesh->ny;
+  a.nz = sp->mesh->nz;
   a.constrained = constrained;
   a.skip = skip;
+  const int im = op->index_mode;
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
-    PAFEM_TRY(ensure_et(sp));
     PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
     a.yE = op->d_evec.as<T>();
-    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, a, s));
-    PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(), sp->d_et_idx.as<int32_t>(),
-                                      a.ess_mask, constrained, accumulate, x, y, sp->ndofs, skip,
-                                      s));
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, im, a, s));
+    if (im == PAFEM_INDEX_MAP) {
+      PAFEM_TRY(ensure_et(sp));
+      PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(),
+                                        sp->d_et_idx.as<int32_t>(), a.ess_mask, constrained,
+                                        accumulate, x, y, sp->ndofs, skip, s));
+    } else {
+      PAFEM_TRY_HIP(launch_gather_lattice<T>(a.yE, a.nx, a.ny, a.nz, sp->p, constrained,
+                                             accumulate, x, y, skip, s));
+    }
   } else {
     // zero y with a kernel (not a memset) so the sequence can sit in a captured graph
     if (!accumulate) PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
     if (constrained)
       PAFEM_TRY_HIP(launch_set_ess<T>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), x, T(0),
                                       accumulate, y, skip, s));
-    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_ATOMIC, a, s));
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_ATOMIC, im, a, s));
   }
   return PAFEM_OK;
 }
@@ -479,6 +488,14 @@ int pafem_op_set_scatter_mode(pafem_op* op, int mode) {
   CHECK_ARG(mode == PAFEM_SCATTER_ATOMIC || mode == PAFEM_SCATTER_DETERMINISTIC,
             "unknown scatter mode");
   op->scatter_mode = mode;
+  return PAFEM_OK;
+}
+
+int pafem_op_set_restriction_mode(pafem_op* op, int mode) {
+  clear_error();
+  CHECK_ARG(op, "NULL argument");
+  CHECK_ARG(mode == PAFEM_INDEX_LATTICE || mode == PAFEM_INDEX_MAP, "unknown restriction mode");
+  op->index_mode = mode;
   return PAFEM_OK;
 }
 

@@ -148,6 +148,7 @@ struct Op : RefCounted {
   DevBuf d_qd64, d_qd32;        // quadrature data
   bool have64 = false, have32 = false;
   int scatter_mode = PAFEM_SCATTER_ATOMIC;
+  int index_mode = PAFEM_INDEX_LATTICE;
   DevBuf d_evec;                // E-vector workspace (deterministic scatter, diagonal, rhs)
   DevBuf d_flag;                // int error flag for assembly
   // solver workspace
@@ -193,14 +194,15 @@ struct ApplyArgs {
   const T* B;         // [q][n]
   const T* G;         // [q][n]
   int64_t ne;
+  int nx, ny, nz;     // element lattice (lattice-computed restriction)
   int constrained;
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
 };
 
 // y (atomic) or yE (deterministic) from one fused sum-factorized element pass.
 template <typename T>
-hipError_t launch_apply(int kind, int p, int q, int scatter_mode, const ApplyArgs<T>& a,
-                        hipStream_t s);
+hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode,
+                        const ApplyArgs<T>& a, hipStream_t s);
 
 // Element-diagonal (E-vector) by sum factorization.
 hipError_t launch_diag_elem(int kind, int p, int q, const double* qd, const double* B,
@@ -215,6 +217,12 @@ template <typename T>
 hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
                             const uint8_t* ess_mask, int constrained, int accumulate, const T* x,
                             T* y, int64_t ndofs, const int* skip, hipStream_t s);
+// The same sum with the E-vector positions of each dof computed from the
+// lattice (same ascending (e, l) order, so bitwise equal to the CSR form).
+template <typename T>
+hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
+                                 int accumulate, const T* x, T* y, const int* skip,
+                                 hipStream_t s);
 
 // Essential-dof fix-up: y[ess[i]] (+)= x ? x[ess[i]] : value.
 template <typename T>

@@ -66,6 +66,58 @@ __global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
+// Elements (and local index) containing lattice coordinate I along one
+// direction with n elements of order p: two at an interior element face.
+__device__ __forceinline__ int lattice_cands(int I, int n, int p, int (&e)[2], int (&l)[2]) {
+  if (I % p == 0 && I > 0 && I < n * p) {
+    e[0] = I / p - 1;
+    l[0] = p;
+    e[1] = I / p;
+    l[1] = 0;
+    return 2;
+  }
+  int ee = I / p;
+  if (ee > n - 1) ee = n - 1;
+  e[0] = ee;
+  l[0] = I - ee * p;
+  return 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict__ yE, int nx,
+                                                             int ny, int nz, int p,
+                                                             int constrained, int accumulate,
+                                                             const T* __restrict__ x,
+                                                             T* __restrict__ y, const int* skip) {
+  if (skip != nullptr && *skip) return;
+  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Lx * Ly * Lz) return;
+  const int I = (int)(i % Lx);
+  const int J = (int)((i / Lx) % Ly);
+  const int K = (int)(i / (Lx * Ly));
+  T acc = 0;
+  const bool ess = I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1;
+  if (constrained && ess) {
+    acc = x ? x[i] : T(0);
+  } else {
+    const int n = p + 1;
+    const int64_t nloc = (int64_t)n * n * n;
+    int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
+    const int cx = lattice_cands(I, nx, p, ex, lx);
+    const int cy = lattice_cands(J, ny, p, ey, ly);
+    const int cz = lattice_cands(K, nz, p, ez, lz);
+    // ascending element number: z outermost, x innermost
+    for (int kz = 0; kz < cz; ++kz)
+      for (int ky = 0; ky < cy; ++ky)
+        for (int kx = 0; kx < cx; ++kx) {
+          const int64_t e = ex[kx] + (int64_t)nx * (ey[ky] + (int64_t)ny * ez[kz]);
+          acc += yE[e * nloc + lx[kx] + n * (ly[ky] + n * lz[kz])];
+        }
+  }
+  y[i] = accumulate ? y[i] + acc : acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_set_ess(const int32_t* __restrict__ ess, int64_t n,
                                                       const T* __restrict__ x, T value,
@@ -307,6 +359,20 @@ template hipError_t launch_gather_et<double>(const double*, const int32_t*, cons
 template hipError_t launch_gather_et<float>(const float*, const int32_t*, const int32_t*,
                                             const uint8_t*, int, int, const float*, float*,
                                             int64_t, const int*, hipStream_t);
+
+template <typename T>
+hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
+                                 int accumulate, const T* x, T* y, const int* skip,
+                                 hipStream_t s) {
+  const int64_t n = ((int64_t)nx * p + 1) * ((int64_t)ny * p + 1) * ((int64_t)nz * p + 1);
+  hipLaunchKernelGGL((k_gather_lattice<T>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     s, yE, nx, ny, nz, p, constrained, accumulate, x, y, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int,
+                                                  const double*, double*, const int*, hipStream_t);
+template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int,
+                                                 const float*, float*, const int*, hipStream_t);
 
 template <typename T>
 hipError_t launch_set_ess(const int32_t* ess, int64_t n_ess, const T* x, T value, int accumulate,

@@ -22,6 +22,8 @@ FP64 = 1
 FP32 = 2
 SCATTER_ATOMIC = 0
 SCATTER_DETERMINISTIC = 1
+INDEX_LATTICE = 0
+INDEX_MAP = 1
 APPLY_CONSTRAINED = 1
 APPLY_ACCUMULATE = 2
 SOLVE_PLAIN_FP64 = 0
@@ -85,6 +87,7 @@ _SIGNATURES = {
     "pafem_op_qdata_bytes": (_I64, [_P, _I]),
     "pafem_op_get_qdata": (_I, [_P, _I, _P, _P]),
     "pafem_op_set_scatter_mode": (_I, [_P, _I]),
+    "pafem_op_set_restriction_mode": (_I, [_P, _I]),
     "pafem_op_apply": (_I, [_P, _I, _P, _P, _I, _P]),
     "pafem_op_diagonal": (_I, [_P, _P, _I, _P]),
     "pafem_rhs_assemble": (_I, [_P, _P, _P, _P]),
@@ -330,6 +333,9 @@ class Operator:
 
     def set_scatter_mode(self, mode: int):
         _check(lib().pafem_op_set_scatter_mode(self._h, mode))
+
+    def set_restriction_mode(self, mode: int):
+        _check(lib().pafem_op_set_restriction_mode(self._h, mode))
 
     def apply(self, x, y=None, constrained: bool = False, accumulate: bool = False,
               stream=None):

@@ -20,6 +20,12 @@ torch = pytest.importorskip("torch")
 MESHES = [(5, 2, 2), (3, 3, 1)]  # 20 and 9 elements: several workgroups, ragged last one
 
 
+def MODES(pf):
+    """Every (E^T scatter, E source) combination the apply kernels implement."""
+    return [(s, i) for s in (pf.SCATTER_ATOMIC, pf.SCATTER_DETERMINISTIC)
+            for i in (pf.INDEX_LATTICE, pf.INDEX_MAP)]
+
+
 @pytest.fixture(scope="module")
 def pf():
     from paper_2402_15940_amd import pafem
@@ -122,8 +128,9 @@ def test_apply_fp64_matches_oracle(pf, ctx, kind, p, mesh):
     x = inputs.random_vector(n, inputs.vector_seed(p, nx))
     xd = torch.from_numpy(x).cuda()
     ess = fem.essential_dofs(nx, ny, nz, p)
-    for mode in (pf.SCATTER_ATOMIC, pf.SCATTER_DETERMINISTIC):
+    for mode, im in MODES(pf):
         op.set_scatter_mode(mode)
+        op.set_restriction_mode(im)
         y = op.apply(xd).cpu().numpy()
         e2, einf = _relerr(y, A @ x)
         assert e2 <= 1e-12 and einf <= 1e-12, (mode, e2, einf)
@@ -163,8 +170,9 @@ def test_apply_fp32_close_to_oracle(pf, ctx, p):
         A = _oracle_matrix(kind, nx, ny, nz, p, seed, None)
         v, op = _build(pf, ctx, kind, nx, ny, nz, p, seed, prec=pf.FP64 | pf.FP32)
         x = inputs.random_vector(op.space.ndofs, 9)
-        for mode in (pf.SCATTER_ATOMIC, pf.SCATTER_DETERMINISTIC):
+        for mode, im in MODES(pf):
             op.set_scatter_mode(mode)
+            op.set_restriction_mode(im)
             y = op.apply(torch.from_numpy(x).float().cuda()).double().cpu().numpy()
             e2, _ = _relerr(y, A @ x.astype(np.float32).astype(np.float64))
             assert e2 <= 5e-5, e2
@@ -197,6 +205,10 @@ def test_deterministic_mode_is_bitwise_reproducible(pf, ctx):
     y1 = op.apply(x).clone()
     y2 = op.apply(x).clone()
     assert torch.equal(y1, y2)
+    # the lattice-computed and the stored E^T sum in the same order
+    op.set_restriction_mode(pf.INDEX_MAP)
+    y3 = op.apply(x).clone()
+    assert torch.equal(y1, y3)
     d1 = op.diagonal()
     d2 = op.diagonal()
     assert torch.equal(d1, d2)
@@ -355,8 +367,9 @@ def test_full_size_sampled_rows(pf, ctx, p, target):
     for kind in ("diffusion", "mass"):
         op = pf.Operator(sp, pf.DIFFUSION if kind == "diffusion" else pf.MASS)
         op.assemble()
-        for mode in (pf.SCATTER_ATOMIC, pf.SCATTER_DETERMINISTIC):
+        for mode, im in MODES(pf):
             op.set_scatter_mode(mode)
+            op.set_restriction_mode(im)
             y = op.apply(xd)[torch.from_numpy(dofs).cuda()].cpu().numpy()
             yo = _oracle_rows(kind, v, N, N, N, p, x, dofs)
             scale = np.abs(yo).max()
@@ -419,8 +432,9 @@ def test_apply_accumulate(pf, ctx, kind):
     x = inputs.random_vector(n, 1)
     y0 = inputs.random_vector(n, 2)
     ess = fem.essential_dofs(nx, ny, nz, p)
-    for mode in (pf.SCATTER_ATOMIC, pf.SCATTER_DETERMINISTIC):
+    for mode, im in MODES(pf):
         op.set_scatter_mode(mode)
+        op.set_restriction_mode(im)
         for constrained in (False, True):
             y = torch.from_numpy(y0.copy()).cuda()
             op.apply(torch.from_numpy(x).cuda(), y, constrained=constrained, accumulate=True)
