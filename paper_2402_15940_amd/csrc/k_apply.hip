@@ -4,15 +4,19 @@
 // line of the element and the full 1D table, so the tables are wave-uniform
 // (scalar-register operands) and LDS carries each intermediate exactly once:
 //
-//   A   x contraction   line (b, c):   gather x_e(:, b, c)  -> B x, G x      (per qx)
-//   B   y contraction   line (qx, c):  -> (B,B) (G,B) (B,G) factors         (per qy)
+//   A   y contraction   line (a, c):   gather x_e(a, :, c)  -> B x, G x      (per qy)
+//   B   x contraction   line (qy, c):  -> (B,B) (G,B) (B,G) factors         (per qx)
 //   C   z contraction   line (qx, qy): -> reference gradient at every qz,
 //                                         pointwise D (6 stored factors),
 //                                         transposed z contraction
-//   B^T y contraction   line (qx, c)
-//   A^T x contraction   line (b, c):   -> y_e(:, b, c)  -> scatter (E^T)
+//   B^T x contraction   line (qy, c)
+//   A^T y contraction   line (a, c):   -> y_e(a, :, c)  -> scatter (E^T)
 //
-// LDS holds, per element, one private region of R words for every (c, qx)
+// Lanes of stages A/A^T run along x, so the gather and the scatter-add touch
+// consecutive dofs; lanes of stage C run along qx, so the quadrature-data
+// stream is read in contiguous runs.
+//
+// LDS holds, per element, one private region of R words for every (c, qy)
 // pair; each stage reads its line's inputs from the regions it owns and
 // writes its outputs back into the same regions, so one buffer of N*Q*R words
 // serves every stage (R = max(2N, 3Q) rounded up to an odd count, which keeps
@@ -115,7 +119,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS)) void k_ap
   const T* __restrict__ Bt = a.B;
   const T* __restrict__ Gt = a.G;
 
-  // stage-C role of this thread: line (qx, qy) of element slot sC
+  // stage-C role of this thread: z-line (qx, qy) of element slot sC
   const int sC = tid / QQ, rC = tid - sC * QQ;
   const int64_t eC = e0 + sC;
   const bool actC = sC < NE && eC < a.ne;
@@ -132,69 +136,70 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS)) void k_ap
       for (int qz = 0; qz < Q; ++qz) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
   }
 
-  // ---- stage A: gather + x contraction, line (b, c) ----
-  {
-    const int s = tid / (N * N), r = tid - s * (N * N);
-    const int64_t e = e0 + s;
-    if (s < NE && e < a.ne) {
-      const int b = r % N, c = r / N;
-      Restrict<P, IDX, T> E;
-      E.init(a, e);
-      T u[N];
+  // stage-A role: y-line (a, c); lanes run along x so gather and scatter coalesce
+  const int sA = tid / (N * N), rA = tid - sA * (N * N);
+  const int64_t eA = e0 + sA;
+  const bool actA = sA < NE && eA < a.ne;
+  const int aA = rA % N, cA = rA / N;
+
+  // ---- stage A: gather + y contraction ----
+  if (actA) {
+    Restrict<P, IDX, T> E;
+    E.init(a, eA);
+    T u[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int32_t g = E.dof(i, b, c);
-        T v = a.x[g];
-        if (a.constrained && E.ess(a, g, i, b, c)) v = T(0);
-        u[i] = v;
+    for (int b = 0; b < N; ++b) {
+      const int32_t g = E.dof(aA, b, cA);
+      T v = a.x[g];
+      if (a.constrained && E.ess(a, g, aA, b, cA)) v = T(0);
+      u[b] = v;
+    }
+    T* reg = smem + sA * L + (cA * Q) * R + aA;  // region (c, qy) at + qy*R
+#pragma unroll
+    for (int qy = 0; qy < Q; ++qy) {
+      T tb = 0, tg = 0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        tb += Bt[qy * N + b] * u[b];
+        tg += Gt[qy * N + b] * u[b];
       }
-      T* reg = smem + s * L + (c * Q) * R;
-#pragma unroll
-      for (int qx = 0; qx < Q; ++qx) {
-        T tb = 0, tg = 0;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          tb += Bt[qx * N + i] * u[i];
-          tg += Gt[qx * N + i] * u[i];
-        }
-        reg[qx * R + b] = tb;
-        reg[qx * R + N + b] = tg;
-      }
+      reg[qy * R] = tb;
+      reg[qy * R + N] = tg;
     }
   }
   __syncthreads();
 
-  // ---- stage B: y contraction, line (qx, c) ----
+  // ---- stage B: x contraction, x-line (qy, c) ----
   const int sB = tid / (Q * N), rB = tid - sB * (Q * N);
   const bool actB = sB < NE && e0 + sB < a.ne;
-  const int qxB = rB % Q, cB = rB / Q;
+  const int qyB = rB % Q, cB = rB / Q;
   if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qxB) * R;
+    T* reg = smem + sB * L + (cB * Q + qyB) * R;
     T tb[N], tg[N];
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      tb[b] = reg[b];
-      tg[b] = reg[N + b];
+    for (int i = 0; i < N; ++i) {
+      tb[i] = reg[i];
+      tg[i] = reg[N + i];
     }
 #pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-      T bb = 0, gb = 0, bg = 0;
+    for (int qx = 0; qx < Q; ++qx) {
+      T bb = 0, gb = 0, bg = 0;  // factors (x, y): (B,B) (G,B) (B,G)
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        bb += Bt[qy * N + b] * tb[b];
-        gb += Bt[qy * N + b] * tg[b];
-        bg += Gt[qy * N + b] * tb[b];
+      for (int i = 0; i < N; ++i) {
+        bb += Bt[qx * N + i] * tb[i];
+        gb += Gt[qx * N + i] * tb[i];
+        bg += Bt[qx * N + i] * tg[i];
       }
-      reg[qy] = bb;
-      reg[Q + qy] = gb;
-      reg[2 * Q + qy] = bg;
+      reg[qx] = bb;
+      reg[Q + qx] = gb;
+      reg[2 * Q + qx] = bg;
     }
   }
   __syncthreads();
 
   // ---- stage C: z contraction, pointwise D, transposed z contraction ----
   if (actC) {
-    T* reg0 = smem + sC * L + qxC * R + qyC;  // + c*Q*R + k*Q
+    T* reg0 = smem + sC * L + qyC * R + qxC;  // + c*Q*R + k*Q
     T ibb[N], igb[N], ibg[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -233,56 +238,53 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS)) void k_ap
   }
   __syncthreads();
 
-  // ---- stage B^T: transposed y contraction, line (qx, c) ----
+  // ---- stage B^T: transposed x contraction, x-line (qy, c) ----
+  // x-path needs G in x, the y- and z-paths B in x; afterwards the x- and
+  // z-paths share B in y, so they are summed here.
   if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qxB) * R;
+    T* reg = smem + sB * L + (cB * Q + qyB) * R;
     T w1[Q], w2[Q], w3[Q];
 #pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-      w1[qy] = reg[qy];
-      w2[qy] = reg[Q + qy];
-      w3[qy] = reg[2 * Q + qy];
+    for (int qx = 0; qx < Q; ++qx) {
+      w1[qx] = reg[qx];
+      w2[qx] = reg[Q + qx];
+      w3[qx] = reg[2 * Q + qx];
     }
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      T s1 = 0, s23 = 0;
+    for (int i = 0; i < N; ++i) {
+      T s13 = 0, s2 = 0;
 #pragma unroll
-      for (int qy = 0; qy < Q; ++qy) {
-        s1 += Bt[qy * N + b] * w1[qy];
-        s23 += Gt[qy * N + b] * w2[qy] + Bt[qy * N + b] * w3[qy];
+      for (int qx = 0; qx < Q; ++qx) {
+        s13 += Gt[qx * N + i] * w1[qx] + Bt[qx * N + i] * w3[qx];
+        s2 += Bt[qx * N + i] * w2[qx];
       }
-      reg[b] = s1;
-      reg[N + b] = s23;
+      reg[i] = s13;
+      reg[N + i] = s2;
     }
   }
   __syncthreads();
 
-  // ---- stage A^T: transposed x contraction + scatter, line (b, c) ----
-  {
-    const int s = tid / (N * N), r = tid - s * (N * N);
-    const int64_t e = e0 + s;
-    if (s < NE && e < a.ne) {
-      const int b = r % N, c = r / N;
-      const T* reg = smem + s * L + (c * Q) * R;
-      T W1[Q], W23[Q];
+  // ---- stage A^T: transposed y contraction + scatter, y-line (a, c) ----
+  if (actA) {
+    const T* reg = smem + sA * L + (cA * Q) * R + aA;
+    T X13[Q], X2[Q];
 #pragma unroll
-      for (int qx = 0; qx < Q; ++qx) {
-        W1[qx] = reg[qx * R + b];
-        W23[qx] = reg[qx * R + N + b];
-      }
-      Restrict<P, IDX, T> E;
-      E.init(a, e);
+    for (int qy = 0; qy < Q; ++qy) {
+      X13[qy] = reg[qy * R];
+      X2[qy] = reg[qy * R + N];
+    }
+    Restrict<P, IDX, T> E;
+    E.init(a, eA);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = 0;
+    for (int b = 0; b < N; ++b) {
+      T acc = 0;
 #pragma unroll
-        for (int qx = 0; qx < Q; ++qx) acc += Gt[qx * N + i] * W1[qx] + Bt[qx * N + i] * W23[qx];
-        if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
-          a.yE[e * (N * N * N) + (c * N + b) * N + i] = acc;
-        } else {
-          const int32_t g = E.dof(i, b, c);
-          if (!(a.constrained && E.ess(a, g, i, b, c))) scatter_add(a.y + g, acc);
-        }
+      for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * X13[qy] + Gt[qy * N + b] * X2[qy];
+      if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
+        a.yE[eA * (N * N * N) + (cA * N + b) * N + aA] = acc;
+      } else {
+        const int32_t g = E.dof(aA, b, cA);
+        if (!(a.constrained && E.ess(a, g, aA, b, cA))) scatter_add(a.y + g, acc);
       }
     }
   }
@@ -316,53 +318,52 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
     for (int qz = 0; qz < Q; ++qz) dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
   }
 
-  {
-    const int s = tid / (N * N), r = tid - s * (N * N);
-    const int64_t e = e0 + s;
-    if (s < NE && e < a.ne) {
-      const int b = r % N, c = r / N;
-      Restrict<P, IDX, T> E;
-      E.init(a, e);
-      T u[N];
+  const int sA = tid / (N * N), rA = tid - sA * (N * N);
+  const int64_t eA = e0 + sA;
+  const bool actA = sA < NE && eA < a.ne;
+  const int aA = rA % N, cA = rA / N;
+  if (actA) {
+    Restrict<P, IDX, T> E;
+    E.init(a, eA);
+    T u[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int32_t g = E.dof(i, b, c);
-        T v = a.x[g];
-        if (a.constrained && E.ess(a, g, i, b, c)) v = T(0);
-        u[i] = v;
-      }
-      T* reg = smem + s * L + (c * Q) * R;
+    for (int b = 0; b < N; ++b) {
+      const int32_t g = E.dof(aA, b, cA);
+      T v = a.x[g];
+      if (a.constrained && E.ess(a, g, aA, b, cA)) v = T(0);
+      u[b] = v;
+    }
+    T* reg = smem + sA * L + (cA * Q) * R + aA;
 #pragma unroll
-      for (int qx = 0; qx < Q; ++qx) {
-        T tb = 0;
+    for (int qy = 0; qy < Q; ++qy) {
+      T tb = 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) tb += Bt[qx * N + i] * u[i];
-        reg[qx * R + b] = tb;
-      }
+      for (int b = 0; b < N; ++b) tb += Bt[qy * N + b] * u[b];
+      reg[qy * R] = tb;
     }
   }
   __syncthreads();
 
   const int sB = tid / (Q * N), rB = tid - sB * (Q * N);
   const bool actB = sB < NE && e0 + sB < a.ne;
-  const int qxB = rB % Q, cB = rB / Q;
+  const int qyB = rB % Q, cB = rB / Q;
   if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qxB) * R;
+    T* reg = smem + sB * L + (cB * Q + qyB) * R;
     T tb[N];
 #pragma unroll
-    for (int b = 0; b < N; ++b) tb[b] = reg[b];
+    for (int i = 0; i < N; ++i) tb[i] = reg[i];
 #pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
+    for (int qx = 0; qx < Q; ++qx) {
       T bb = 0;
 #pragma unroll
-      for (int b = 0; b < N; ++b) bb += Bt[qy * N + b] * tb[b];
-      reg[qy] = bb;
+      for (int i = 0; i < N; ++i) bb += Bt[qx * N + i] * tb[i];
+      reg[qx] = bb;
     }
   }
   __syncthreads();
 
   if (actC) {
-    T* reg0 = smem + sC * L + qxC * R + qyC;
+    T* reg0 = smem + sC * L + qyC * R + qxC;
     T in[N], w[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -384,42 +385,37 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
   __syncthreads();
 
   if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qxB) * R;
+    T* reg = smem + sB * L + (cB * Q + qyB) * R;
     T w[Q];
 #pragma unroll
-    for (int qy = 0; qy < Q; ++qy) w[qy] = reg[qy];
+    for (int qx = 0; qx < Q; ++qx) w[qx] = reg[qx];
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
+    for (int i = 0; i < N; ++i) {
       T s1 = 0;
 #pragma unroll
-      for (int qy = 0; qy < Q; ++qy) s1 += Bt[qy * N + b] * w[qy];
-      reg[b] = s1;
+      for (int qx = 0; qx < Q; ++qx) s1 += Bt[qx * N + i] * w[qx];
+      reg[i] = s1;
     }
   }
   __syncthreads();
 
-  {
-    const int s = tid / (N * N), r = tid - s * (N * N);
-    const int64_t e = e0 + s;
-    if (s < NE && e < a.ne) {
-      const int b = r % N, c = r / N;
-      const T* reg = smem + s * L + (c * Q) * R;
-      T W[Q];
+  if (actA) {
+    const T* reg = smem + sA * L + (cA * Q) * R + aA;
+    T W[Q];
 #pragma unroll
-      for (int qx = 0; qx < Q; ++qx) W[qx] = reg[qx * R + b];
-      Restrict<P, IDX, T> E;
-      E.init(a, e);
+    for (int qy = 0; qy < Q; ++qy) W[qy] = reg[qy * R];
+    Restrict<P, IDX, T> E;
+    E.init(a, eA);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = 0;
+    for (int b = 0; b < N; ++b) {
+      T acc = 0;
 #pragma unroll
-        for (int qx = 0; qx < Q; ++qx) acc += Bt[qx * N + i] * W[qx];
-        if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
-          a.yE[e * (N * N * N) + (c * N + b) * N + i] = acc;
-        } else {
-          const int32_t g = E.dof(i, b, c);
-          if (!(a.constrained && E.ess(a, g, i, b, c))) scatter_add(a.y + g, acc);
-        }
+      for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * W[qy];
+      if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
+        a.yE[eA * (N * N * N) + (cA * N + b) * N + aA] = acc;
+      } else {
+        const int32_t g = E.dof(aA, b, cA);
+        if (!(a.constrained && E.ess(a, g, aA, b, cA))) scatter_add(a.y + g, acc);
       }
     }
   }
