@@ -97,6 +97,7 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   a.ny = sp->mesh->ny;
   a.nz = sp->mesh->nz;
   a.constrained = constrained;
+  a.accumulate = accumulate;
   a.skip = skip;
   const int im = op->index_mode;
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {

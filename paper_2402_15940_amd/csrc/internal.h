@@ -196,6 +196,7 @@ struct ApplyArgs {
   int64_t ne;
   int nx, ny, nz;     // element lattice (lattice-computed restriction)
   int constrained;
+  int accumulate;     // atomic mode: y holds a previous result to add to
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
 };
 

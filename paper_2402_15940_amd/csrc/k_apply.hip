@@ -33,13 +33,21 @@ namespace {
 
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
+// Launch tuning, measured on MI355X (overridable at build time for sweeps):
+// elements per workgroup by q, and the waves per SIMD the register allocation
+// must leave room for, by p, for the FP64 diffusion kernel.
+#ifndef PAFEM_NE_BY_Q
+#define PAFEM_NE_BY_Q 1, 1, 1, 7, 4, 5, 7, 5, 1, 3, 2
+#endif
+#ifndef PAFEM_WAVES_DIFF_F64
+#define PAFEM_WAVES_DIFF_F64 1, 1, 1, 1, 4, 1, 1, 1, 1
+#endif
+constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
+constexpr int kWavesDiff64[] = {PAFEM_WAVES_DIFF_F64};
+
 __host__ __device__ constexpr int odd_up(int v) { return (v % 2 == 0) ? v + 1 : v; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-// Elements per workgroup for q (one element per q x q thread slice).
-__host__ __device__ constexpr int elems_per_block(int q) {
-  return q == 3 ? 7 : q == 4 ? 4 : q == 5 ? 5 : q == 6 ? 7 : q == 7 ? 5 : q == 8 ? 1 : q == 9 ? 3 : 2;
-}
 
 template <int P, int Q, typename T, int KIND>
 struct Cfg {
@@ -47,8 +55,11 @@ struct Cfg {
   static constexpr int QQ = Q * Q;
   static constexpr int R = KIND == PAFEM_DIFFUSION ? odd_up(cmax(2 * N, 3 * Q)) : odd_up(cmax(N, Q));
   static constexpr int L = N * Q * R;  // LDS words per element
-  static constexpr int NE = elems_per_block(Q);
+  static constexpr int NE = kNeByQ[Q];
   static constexpr int THREADS = ((NE * QQ + 63) / 64) * 64;
+  // waves per SIMD the register allocation must allow (occupancy floor)
+  static constexpr int MIN_WAVES =
+      (KIND == PAFEM_DIFFUSION && sizeof(T) == 8) ? kWavesDiff64[P] : 1;
   static_assert(NE * L * (int)sizeof(T) <= 64 * 1024, "LDS budget");
 };
 
@@ -105,7 +116,8 @@ __device__ __forceinline__ void scatter_add(T* p, T v) {
 // stored as the 6 upper-triangle entries per quadrature point.
 // ---------------------------------------------------------------------------
 template <int P, int Q, typename T, int SCATTER, int IDX>
-__global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS)) void k_apply_diff(
+__global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
+                             (Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES)) void k_apply_diff(
     ApplyArgs<T> a) {
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
   constexpr int N = C::N, QQ = C::QQ, NE = C::NE, L = C::L, R = C::R;
@@ -275,6 +287,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS)) void k_ap
     }
     Restrict<P, IDX, T> E;
     E.init(a, eA);
+    const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       T acc = 0;
@@ -284,7 +297,12 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS)) void k_ap
         a.yE[eA * (N * N * N) + (cA * N + b) * N + aA] = acc;
       } else {
         const int32_t g = E.dof(aA, b, cA);
-        if (!(a.constrained && E.ess(a, g, aA, b, cA))) scatter_add(a.y + g, acc);
+        if (interior && b > 0 && b < P) {
+          // only this element touches its interior nodes (never essential)
+          a.y[g] = a.accumulate ? a.y[g] + acc : acc;
+        } else if (!(a.constrained && E.ess(a, g, aA, b, cA))) {
+          scatter_add(a.y + g, acc);
+        }
       }
     }
   }
@@ -406,6 +424,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
     for (int qy = 0; qy < Q; ++qy) W[qy] = reg[qy * R];
     Restrict<P, IDX, T> E;
     E.init(a, eA);
+    const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       T acc = 0;
@@ -415,7 +434,12 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
         a.yE[eA * (N * N * N) + (cA * N + b) * N + aA] = acc;
       } else {
         const int32_t g = E.dof(aA, b, cA);
-        if (!(a.constrained && E.ess(a, g, aA, b, cA))) scatter_add(a.y + g, acc);
+        if (interior && b > 0 && b < P) {
+          // only this element touches its interior nodes (never essential)
+          a.y[g] = a.accumulate ? a.y[g] + acc : acc;
+        } else if (!(a.constrained && E.ess(a, g, aA, b, cA))) {
+          scatter_add(a.y + g, acc);
+        }
       }
     }
   }

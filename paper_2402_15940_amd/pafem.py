@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpafem.so")
+# PAFEM_LIB selects another build of the library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PAFEM_LIB") or os.path.join(_HERE, "libpafem.so")
 
 MASS = 0
 DIFFUSION = 1
