@@ -66,8 +66,9 @@ extern "C" {
 #define PAFEM_FP64 1 /* vectors double, FP64 quadrature data and contractions */
 #define PAFEM_FP32 2 /* vectors float, FP32 quadrature data (rounded copy)     */
 
-#define PAFEM_SCATTER_ATOMIC 0        /* E^T by FP64/FP32 atomic adds (fast, run-to-run rounding differences) */
-#define PAFEM_SCATTER_DETERMINISTIC 1 /* E^T by E-vector + per-dof ordered sum (bitwise reproducible) */
+#define PAFEM_SCATTER_ATOMIC 0        /* E^T by global atomic adds (run-to-run rounding differences) */
+#define PAFEM_SCATTER_DETERMINISTIC 1 /* E^T by an E-vector and a per-dof sum in fixed (e, l) order:
+                                         bitwise reproducible; the default */
 
 #define PAFEM_INDEX_LATTICE 0 /* E computed from the lattice numbering in the kernels */
 #define PAFEM_INDEX_MAP 1     /* E and E^T read from the stored int32 maps            */
@@ -161,7 +162,7 @@ int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask);
 /* Copy the stored quadrature data of precision `prec` into dst_dev
  * ([ne][C][q^3], C = 1 or 6, double or float). */
 int pafem_op_get_qdata(pafem_op* op, int prec, void* dst_dev, void* stream);
-/* Choose how E^T sums element contributions (default ATOMIC). */
+/* Choose how E^T sums element contributions (default DETERMINISTIC). */
 int pafem_op_set_scatter_mode(pafem_op* op, int mode);
 /* Choose where the kernels take E (and, in deterministic mode, E^T) from:
  * PAFEM_INDEX_LATTICE (default) computes the lattice numbering in the kernel;
@@ -178,6 +179,12 @@ int pafem_op_set_restriction_mode(pafem_op* op, int mode);
  *     the default atomic E^T mode this launches the element kernel alone). */
 int pafem_op_apply(pafem_op* op, int prec, const void* x_dev, void* y_dev, int flags,
                    void* stream);
+/* The element results before assembly: yE_dev[e][l] = (B^T D B E x)_e at local
+ * node l = a + (p+1)(b + (p+1)c), an E-vector of ne*(p+1)^3 entries of the
+ * precision `prec` (one element kernel, no E^T).  flags: 0 or
+ * PAFEM_APPLY_CONSTRAINED (essential entries of x read as 0). */
+int pafem_op_apply_evector(pafem_op* op, int prec, const void* x_dev, void* yE_dev, int flags,
+                           void* stream);
 /* d = diag(A) by sum factorization (double, ndofs); constrained = 1 puts 1 on
  * essential dofs.  Bitwise reproducible. */
 int pafem_op_diagonal(pafem_op* op, double* d_dev, int constrained, void* stream);

@@ -77,16 +77,14 @@ int ensure_et(Space* sp) {
 }
 
 template <typename T>
-int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s) {
+ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* skip) {
   Space* sp = op->space;
   const int n = sp->p + 1;
-  const int constrained = (flags & PAFEM_APPLY_CONSTRAINED) ? 1 : 0;
-  const int accumulate = (flags & PAFEM_APPLY_ACCUMULATE) ? 1 : 0;
   const DevBuf& tab = std::is_same<T, double>::value ? op->d_tab64 : op->d_tab32;
   ApplyArgs<T> a;
   a.x = x;
   a.y = y;
-  a.yE = nullptr;
+  a.yE = yE;
   a.E = sp->d_E.as<int32_t>();
   a.ess_mask = sp->d_ess_mask.as<uint8_t>();
   a.qd = std::is_same<T, double>::value ? (const T*)op->d_qd64.ptr : (const T*)op->d_qd32.ptr;
@@ -96,29 +94,37 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   a.nx = sp->mesh->nx;
   a.ny = sp->mesh->ny;
   a.nz = sp->mesh->nz;
-  a.constrained = constrained;
-  a.accumulate = accumulate;
+  a.constrained = (flags & PAFEM_APPLY_CONSTRAINED) ? 1 : 0;
+  a.accumulate = (flags & PAFEM_APPLY_ACCUMULATE) ? 1 : 0;
   a.skip = skip;
+  return a;
+}
+
+template <typename T>
+int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s) {
+  Space* sp = op->space;
+  const int n = sp->p + 1;
   const int im = op->index_mode;
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
     PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
-    a.yE = op->d_evec.as<T>();
+    ApplyArgs<T> a = make_args<T>(op, x, y, op->d_evec.as<T>(), flags, skip);
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, im, a, s));
     if (im == PAFEM_INDEX_MAP) {
       PAFEM_TRY(ensure_et(sp));
       PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(),
-                                        sp->d_et_idx.as<int32_t>(), a.ess_mask, constrained,
-                                        accumulate, x, y, sp->ndofs, skip, s));
+                                        sp->d_et_idx.as<int32_t>(), a.ess_mask, a.constrained,
+                                        a.accumulate, x, y, sp->ndofs, skip, s));
     } else {
-      PAFEM_TRY_HIP(launch_gather_lattice<T>(a.yE, a.nx, a.ny, a.nz, sp->p, constrained,
-                                             accumulate, x, y, skip, s));
+      PAFEM_TRY_HIP(launch_gather_lattice<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
+                                             a.accumulate, x, y, skip, s));
     }
   } else {
+    ApplyArgs<T> a = make_args<T>(op, x, y, nullptr, flags, skip);
     // zero y with a kernel (not a memset) so the sequence can sit in a captured graph
-    if (!accumulate) PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
-    if (constrained)
+    if (!a.accumulate) PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
+    if (a.constrained)
       PAFEM_TRY_HIP(launch_set_ess<T>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), x, T(0),
-                                      accumulate, y, skip, s));
+                                      a.accumulate, y, skip, s));
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_ATOMIC, im, a, s));
   }
   return PAFEM_OK;
@@ -514,6 +520,32 @@ int pafem_op_apply(pafem_op* op, int prec, const void* x, void* y, int flags, vo
   if (prec == PAFEM_FP32) {
     CHECK_ARG(op->have32, "FP32 quadrature data not assembled");
     return apply_impl<float>(op, (const float*)x, (float*)y, flags, nullptr, S(stream));
+  }
+  set_error("prec must be PAFEM_FP64 or PAFEM_FP32");
+  return PAFEM_ERR_INVALID_ARG;
+}
+
+int pafem_op_apply_evector(pafem_op* op, int prec, const void* x, void* yE, int flags,
+                           void* stream) {
+  clear_error();
+  CHECK_ARG(op && x && yE, "NULL argument");
+  CHECK_ARG(x != yE, "x and yE must not alias");
+  CHECK_ARG((flags & ~PAFEM_APPLY_CONSTRAINED) == 0, "only PAFEM_APPLY_CONSTRAINED is allowed");
+  PAFEM_TRY(need_device(op->space->mesh->ctx));
+  Space* sp = op->space;
+  hipStream_t s = S(stream);
+  if (prec == PAFEM_FP64) {
+    CHECK_ARG(op->have64, "operator not assembled");
+    ApplyArgs<double> a = make_args<double>(op, (const double*)x, nullptr, (double*)yE, flags,
+                                            nullptr);
+    PAFEM_TRY_HIP(launch_apply<double>(op->kind, sp->p, op->q, kScatterEvector, op->index_mode, a, s));
+    return PAFEM_OK;
+  }
+  if (prec == PAFEM_FP32) {
+    CHECK_ARG(op->have32, "FP32 quadrature data not assembled");
+    ApplyArgs<float> a = make_args<float>(op, (const float*)x, nullptr, (float*)yE, flags, nullptr);
+    PAFEM_TRY_HIP(launch_apply<float>(op->kind, sp->p, op->q, kScatterEvector, op->index_mode, a, s));
+    return PAFEM_OK;
   }
   set_error("prec must be PAFEM_FP64 or PAFEM_FP32");
   return PAFEM_ERR_INVALID_ARG;

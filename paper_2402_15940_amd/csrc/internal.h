@@ -147,7 +147,7 @@ struct Op : RefCounted {
   DevBuf d_tab64, d_tab32;      // B[q][n], G[q][n], pts[q], wts[q]
   DevBuf d_qd64, d_qd32;        // quadrature data
   bool have64 = false, have32 = false;
-  int scatter_mode = PAFEM_SCATTER_ATOMIC;
+  int scatter_mode = PAFEM_SCATTER_DETERMINISTIC;
   int index_mode = PAFEM_INDEX_LATTICE;
   DevBuf d_evec;                // E-vector workspace (deterministic scatter, diagonal, rhs)
   DevBuf d_flag;                // int error flag for assembly
@@ -199,6 +199,10 @@ struct ApplyArgs {
   int accumulate;     // atomic mode: y holds a previous result to add to
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
 };
+
+// Internal E^T mode: the full E-vector [ne][(p+1)^3] (element results before
+// assembly), used by pafem_op_apply_evector.
+constexpr int kScatterEvector = 2;
 
 // y (atomic) or yE (deterministic) from one fused sum-factorized element pass.
 template <typename T>

@@ -111,6 +111,29 @@ __device__ __forceinline__ void scatter_add(T* p, T v) {
   atomicAdd(p, v);
 }
 
+// Where one element result goes:
+//   atomic         global FP64/FP32 atomic add into y (memory-side on MI355X);
+//   deterministic  element-interior nodes (owned by this element alone) are
+//                  stored to y directly when E is the lattice numbering; every
+//                  other node goes to the E-vector for the ordered per-dof sum;
+//   E-vector       every node goes to the E-vector.
+template <int P, int SCATTER, int IDX, typename T>
+__device__ __forceinline__ void store_result(const ApplyArgs<T>& a, const Restrict<P, IDX, T>& E,
+                                             int64_t e, int aa, int b, int c, bool interior,
+                                             T acc) {
+  constexpr int N = P + 1;
+  if (SCATTER == kScatterEvector ||
+      (SCATTER == PAFEM_SCATTER_DETERMINISTIC && (IDX == PAFEM_INDEX_MAP || !interior))) {
+    a.yE[e * (N * N * N) + (c * N + b) * N + aa] = acc;
+  } else if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
+    const int32_t g = E.dof(aa, b, c);
+    a.y[g] = a.accumulate ? a.y[g] + acc : acc;
+  } else {
+    const int32_t g = E.dof(aa, b, c);
+    if (!(a.constrained && E.ess(a, g, aa, b, c))) scatter_add(a.y + g, acc);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // diffusion: y_e = sum_ij G_i^T S_ij G_j x_e, S = w k adj(J) adj(J)^T / detJ
 // stored as the 6 upper-triangle entries per quadrature point.
@@ -293,17 +316,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
       T acc = 0;
 #pragma unroll
       for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * X13[qy] + Gt[qy * N + b] * X2[qy];
-      if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
-        a.yE[eA * (N * N * N) + (cA * N + b) * N + aA] = acc;
-      } else {
-        const int32_t g = E.dof(aA, b, cA);
-        if (interior && b > 0 && b < P) {
-          // only this element touches its interior nodes (never essential)
-          a.y[g] = a.accumulate ? a.y[g] + acc : acc;
-        } else if (!(a.constrained && E.ess(a, g, aA, b, cA))) {
-          scatter_add(a.y + g, acc);
-        }
-      }
+      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
     }
   }
 }
@@ -430,17 +443,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
       T acc = 0;
 #pragma unroll
       for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * W[qy];
-      if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
-        a.yE[eA * (N * N * N) + (cA * N + b) * N + aA] = acc;
-      } else {
-        const int32_t g = E.dof(aA, b, cA);
-        if (interior && b > 0 && b < P) {
-          // only this element touches its interior nodes (never essential)
-          a.y[g] = a.accumulate ? a.y[g] + acc : acc;
-        } else if (!(a.constrained && E.ess(a, g, aA, b, cA))) {
-          scatter_add(a.y + g, acc);
-        }
-      }
+      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
     }
   }
 }
@@ -463,7 +466,10 @@ hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s) {
 template <int P, typename T, int KIND>
 hipError_t apply_kind(int scatter, int idx, const ApplyArgs<T>& a, hipStream_t s) {
   constexpr int DET = PAFEM_SCATTER_DETERMINISTIC, ATO = PAFEM_SCATTER_ATOMIC;
+  constexpr int EVC = kScatterEvector;
   constexpr int MAP = PAFEM_INDEX_MAP, LAT = PAFEM_INDEX_LATTICE;
+  if (scatter == EVC)
+    return idx == MAP ? launch_one<P, T, KIND, EVC, MAP>(a, s) : launch_one<P, T, KIND, EVC, LAT>(a, s);
   if (scatter == DET)
     return idx == MAP ? launch_one<P, T, KIND, DET, MAP>(a, s) : launch_one<P, T, KIND, DET, LAT>(a, s);
   return idx == MAP ? launch_one<P, T, KIND, ATO, MAP>(a, s) : launch_one<P, T, KIND, ATO, LAT>(a, s);

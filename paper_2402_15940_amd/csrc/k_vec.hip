@@ -96,6 +96,8 @@ __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict
   const int I = (int)(i % Lx);
   const int J = (int)((i / Lx) % Ly);
   const int K = (int)(i / (Lx * Ly));
+  // element-interior nodes were stored directly by the element kernel
+  if (I % p != 0 && J % p != 0 && K % p != 0) return;
   T acc = 0;
   const bool ess = I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1;
   if (constrained && ess) {

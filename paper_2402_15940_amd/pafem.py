@@ -90,6 +90,7 @@ _SIGNATURES = {
     "pafem_op_set_scatter_mode": (_I, [_P, _I]),
     "pafem_op_set_restriction_mode": (_I, [_P, _I]),
     "pafem_op_apply": (_I, [_P, _I, _P, _P, _I, _P]),
+    "pafem_op_apply_evector": (_I, [_P, _I, _P, _P, _I, _P]),
     "pafem_op_diagonal": (_I, [_P, _P, _I, _P]),
     "pafem_rhs_assemble": (_I, [_P, _P, _P, _P]),
     "pafem_solve_cg": (_I, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveStats), _P]),
@@ -351,6 +352,19 @@ class Operator:
         _check(lib().pafem_op_apply(self._h, prec, _dptr(x, x.dtype, n, "x"),
                                     _dptr(y, x.dtype, n, "y"), flags, _stream(stream)))
         return y
+
+    def apply_evector(self, x, yE=None, constrained: bool = False, stream=None):
+        """Element results before assembly, shape [nelems, (p+1)^3]."""
+        torch = self._torch()
+        prec = FP64 if x.dtype == torch.float64 else FP32
+        m = self.space.nelems * (self.space.p + 1) ** 3
+        if yE is None:
+            yE = torch.empty(m, dtype=x.dtype, device=x.device)
+        _check(lib().pafem_op_apply_evector(self._h, prec, _dptr(x, x.dtype, self.space.ndofs, "x"),
+                                            _dptr(yE, x.dtype, m, "yE"),
+                                            APPLY_CONSTRAINED if constrained else 0,
+                                            _stream(stream)))
+        return yE.view(self.space.nelems, (self.space.p + 1) ** 3)
 
     def diagonal(self, constrained: bool = False, out=None, stream=None):
         torch = self._torch()

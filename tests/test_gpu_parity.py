@@ -441,3 +441,29 @@ def test_apply_accumulate(pf, ctx, kind):
             Ax = fem.constrained_apply(A, x, ess) if constrained else A @ x
             e2, einf = _relerr(y.cpu().numpy(), y0 + Ax)
             assert e2 <= 1e-12 and einf <= 1e-12, (mode, constrained, e2)
+
+
+@pytest.mark.parametrize("p", [1, 3, 6, 8])
+@pytest.mark.parametrize("kind", ["mass", "diffusion"])
+def test_apply_evector_is_element_matrix_action(pf, ctx, kind, p):
+    nx, ny, nz = 3, 2, 1
+    v, op = _build(pf, ctx, kind, nx, ny, nz, p, seed=60 + p, prec=pf.FP64 | pf.FP32)
+    x = inputs.random_vector(op.space.ndofs, 3)
+    E = fem.element_restriction(nx, ny, nz, p)
+    EV = fem.element_vertices(v, nx, ny, nz)
+    fn = fem.element_mass if kind == "mass" else fem.element_diffusion
+    ess = np.zeros(op.space.ndofs, bool)
+    ess[fem.essential_dofs(nx, ny, nz, p)] = True
+    xt = np.where(ess, 0.0, x)
+    for im in (pf.INDEX_LATTICE, pf.INDEX_MAP):
+        op.set_restriction_mode(im)
+        yE = op.apply_evector(torch.from_numpy(x).cuda()).cpu().numpy()
+        yEc = op.apply_evector(torch.from_numpy(x).cuda(), constrained=True).cpu().numpy()
+        y32 = op.apply_evector(torch.from_numpy(x).float().cuda()).double().cpu().numpy()
+        for e in range(len(E)):
+            Ae = fn(EV[e], p, p + 2)
+            ref = Ae @ x[E[e]]
+            np.testing.assert_allclose(yE[e], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+            refc = Ae @ xt[E[e]]
+            np.testing.assert_allclose(yEc[e], refc, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+            np.testing.assert_allclose(y32[e], ref, rtol=1e-4, atol=5e-5 * np.abs(ref).max())
