@@ -8,10 +8,10 @@ input vector U[-1,1]; `value` is GDOF/s over the timed applies with all data
 already resident in HBM.
 
 The same JSON line also reports
-  * roofline: the element kernel alone (accumulate mode launches nothing
-    else), timed with HIP events on the stream it runs on, against 8 TB/s,
-    with the algorithmic bytes per launch (quadrature data + E map + x read +
-    y write);
+  * roofline: the element pass alone (pafem_op_apply_evector launches
+    exactly that kernel), timed with HIP events on the stream it runs on,
+    against 8 TB/s, with the algorithmic bytes of one apply (quadrature data +
+    x read + y write; the restriction is computed, not read);
   * cpu_baseline: the CPU oracle (CSR SpMV of the fully assembled matrix) on a
     bounded sample of the same workload (p = 6, smaller mesh), in GDOF/s;
   * cg: GDOF/s per Jacobi-PCG iteration in FP64 and in the FP32 inner solve;
@@ -44,9 +44,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def apply_bytes(ne, n, q, ncomp, ndofs, s):
-    """Algorithmic HBM bytes of one apply: quadrature data, int32 E map, x read, y write."""
-    return ne * q ** 3 * ncomp * s + ne * n ** 3 * 4 + 2 * ndofs * s
+def apply_bytes(ne, n, q, ncomp, ndofs, s, emap=False):
+    """Algorithmic HBM bytes of one apply: quadrature data, x read, y write, plus the
+    int32 E map when the kernels read it (the lattice-computed restriction does not)."""
+    return ne * q ** 3 * ncomp * s + (ne * n ** 3 * 4 if emap else 0) + 2 * ndofs * s
 
 
 def apply_flops(ne, n, q, kind):
@@ -216,7 +217,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_apply_diff<{p},{q},double,E-vector,lattice>", "kernel_ms": round(ms_k, 5),
                 "algorithmic_bytes_per_launch": algo,
-                "algorithmic_bytes": "quadrature data 48 B/qpt + int32 E map 4 B/node + x read + y write",
+                "algorithmic_bytes": "quadrature data 48 B/qpt + x read + y write (E computed, not read)",
                 "flops_per_launch": apply_flops(ne, n, q, "diffusion"),
                 "fp64_tflops": round(apply_flops(ne, n, q, "diffusion") / (ms_k * 1e-3) / 1e12, 2)}
     log(f"element kernel {ms_k:.4f} ms -> {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM)")
