@@ -69,10 +69,56 @@ inline const double* tabWts(const DevBuf& b, int q, int n) {
 
 }  // namespace
 
-int ensure_et(Space* sp) {
-  if (sp->d_et_off.ptr) return PAFEM_OK;
+int ensure_host_maps(Space* sp) {
+  if (sp->have_maps) return PAFEM_OK;
+  const Mesh* m = sp->mesh;
+  try {
+    build_restriction(m->nx, m->ny, m->nz, sp->p, sp->E);
+    build_restriction_transpose(sp->E, sp->ndofs, sp->et_off, sp->et_idx);
+    std::vector<int32_t> ess;
+    build_essential(m->nx, m->ny, m->nz, sp->p, ess, sp->ess_mask);
+  } catch (const std::bad_alloc&) {
+    set_error("host memory exhausted building the integer maps");
+    return PAFEM_ERR_OUT_OF_MEMORY;
+  }
+  sp->have_maps = true;
+  return PAFEM_OK;
+}
+
+int ensure_device_maps(Space* sp) {
+  if (sp->have_dev_maps) return PAFEM_OK;
+  PAFEM_TRY(ensure_host_maps(sp));
+  PAFEM_TRY(upload(sp->d_E, sp->E.data(), sp->E.size()));
   PAFEM_TRY(upload(sp->d_et_off, sp->et_off.data(), sp->et_off.size()));
   PAFEM_TRY(upload(sp->d_et_idx, sp->et_idx.data(), sp->et_idx.size()));
+  PAFEM_TRY(upload(sp->d_ess_mask, sp->ess_mask.data(), sp->ess_mask.size()));
+  sp->have_dev_maps = true;
+  return PAFEM_OK;
+}
+
+// Ascending list of the boundary nodes of the lattice (surface only, so cheap).
+int ensure_ess(Space* sp, bool device) {
+  if (!sp->have_ess) {
+    const int p = sp->p;
+    const int64_t lx = (int64_t)sp->mesh->nx * p + 1, ly = (int64_t)sp->mesh->ny * p + 1,
+                  lz = (int64_t)sp->mesh->nz * p + 1;
+    sp->ess.clear();
+    for (int64_t K = 0; K < lz; ++K)
+      for (int64_t J = 0; J < ly; ++J) {
+        const bool face = K == 0 || K == lz - 1 || J == 0 || J == ly - 1;
+        if (face) {
+          for (int64_t I = 0; I < lx; ++I) sp->ess.push_back((int32_t)(I + lx * (J + ly * K)));
+        } else {
+          sp->ess.push_back((int32_t)(lx * (J + ly * K)));
+          sp->ess.push_back((int32_t)(lx - 1 + lx * (J + ly * K)));
+        }
+      }
+    sp->have_ess = true;
+  }
+  if (device && !sp->have_dev_ess) {
+    PAFEM_TRY(upload(sp->d_ess, sp->ess.data(), sp->ess.size()));
+    sp->have_dev_ess = true;
+  }
   return PAFEM_OK;
 }
 
@@ -81,7 +127,7 @@ ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* sk
   Space* sp = op->space;
   const int n = sp->p + 1;
   const DevBuf& tab = std::is_same<T, double>::value ? op->d_tab64 : op->d_tab32;
-  ApplyArgs<T> a;
+  ApplyArgs<T> a{};
   a.x = x;
   a.y = y;
   a.yE = yE;
@@ -105,18 +151,20 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   Space* sp = op->space;
   const int n = sp->p + 1;
   const int im = op->index_mode;
+  if (im == PAFEM_INDEX_MAP) PAFEM_TRY(ensure_device_maps(sp));
+  if (op->scatter_mode == PAFEM_SCATTER_ATOMIC && (flags & PAFEM_APPLY_CONSTRAINED))
+    PAFEM_TRY(ensure_ess(sp, true));
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
     PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
     ApplyArgs<T> a = make_args<T>(op, x, y, op->d_evec.as<T>(), flags, skip);
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, im, a, s));
     if (im == PAFEM_INDEX_MAP) {
-      PAFEM_TRY(ensure_et(sp));
       PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(),
                                         sp->d_et_idx.as<int32_t>(), a.ess_mask, a.constrained,
                                         a.accumulate, x, y, sp->ndofs, skip, s));
     } else {
       PAFEM_TRY_HIP(launch_gather_lattice<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
-                                             a.accumulate, x, y, skip, s));
+                                             a.accumulate, 1, x, y, skip, s));
     }
   } else {
     ApplyArgs<T> a = make_args<T>(op, x, y, nullptr, flags, skip);
@@ -130,19 +178,34 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   return PAFEM_OK;
 }
 
+// y = E^T yE over every node (constrained: essential rows set to 0), in the
+// op's restriction mode.
+int gather_full(Op* op, const double* yE, int constrained, double* y, hipStream_t s) {
+  Space* sp = op->space;
+  if (op->index_mode == PAFEM_INDEX_MAP) {
+    PAFEM_TRY(ensure_device_maps(sp));
+    PAFEM_TRY_HIP(launch_gather_et<double>(yE, sp->d_et_off.as<int32_t>(),
+                                           sp->d_et_idx.as<int32_t>(),
+                                           sp->d_ess_mask.as<uint8_t>(), constrained, 0, nullptr,
+                                           y, sp->ndofs, nullptr, s));
+  } else {
+    PAFEM_TRY_HIP(launch_gather_lattice<double>(yE, sp->mesh->nx, sp->mesh->ny, sp->mesh->nz,
+                                                sp->p, constrained, 0, 0, nullptr, y, nullptr, s));
+  }
+  return PAFEM_OK;
+}
+
 int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
+  // element diagonals into the E-vector, then the ordered per-dof sum over all
+  // nodes; essential rows are fixed up by the caller
+  (void)constrained;
   Space* sp = op->space;
   const int n = sp->p + 1;
-  PAFEM_TRY(ensure_et(sp));
   PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
   PAFEM_TRY_HIP(launch_diag_elem(op->kind, sp->p, op->q, op->d_qd64.as<double>(),
                                  tabB<double>(op->d_tab64), tabG<double>(op->d_tab64, op->q, n),
                                  sp->ne, op->d_evec.as<double>(), s));
-  // constrained rows get 1 (x = nullptr means 0, so set them afterwards)
-  PAFEM_TRY_HIP(launch_gather_et<double>(op->d_evec.as<double>(), sp->d_et_off.as<int32_t>(),
-                                         sp->d_et_idx.as<int32_t>(), sp->d_ess_mask.as<uint8_t>(),
-                                         0, 0, nullptr, d, sp->ndofs, nullptr, s));
-  return PAFEM_OK;
+  return gather_full(op, op->d_evec.as<double>(), 0, d, s);
 }
 
 template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t);
@@ -285,14 +348,8 @@ int pafem_space_create(pafem_mesh* mesh, int p, pafem_space** out) {
   sp->p = p;
   sp->ne = ne;
   sp->ndofs = ndofs;
-  build_restriction(mesh->nx, mesh->ny, mesh->nz, p, sp->E);
-  build_restriction_transpose(sp->E, ndofs, sp->et_off, sp->et_idx);
-  build_essential(mesh->nx, mesh->ny, mesh->nz, p, sp->ess, sp->ess_mask);
   if (!mesh->ctx->host_only) {
     int rc = need_device(mesh->ctx);
-    if (rc == PAFEM_OK) rc = upload(sp->d_E, sp->E.data(), sp->E.size());
-    if (rc == PAFEM_OK) rc = upload(sp->d_ess, sp->ess.data(), sp->ess.size());
-    if (rc == PAFEM_OK) rc = upload(sp->d_ess_mask, sp->ess_mask.data(), sp->ess_mask.size());
     if (rc != PAFEM_OK) {
       delete sp;
       return rc;
@@ -310,11 +367,17 @@ int pafem_space_destroy(pafem_space* space) {
 
 int64_t pafem_space_ndofs(const pafem_space* s) { return s ? s->ndofs : -1; }
 int64_t pafem_space_nelems(const pafem_space* s) { return s ? s->ne : -1; }
-int64_t pafem_space_num_ess(const pafem_space* s) { return s ? (int64_t)s->ess.size() : -1; }
+int64_t pafem_space_num_ess(const pafem_space* s) {
+  if (!s) return -1;
+  const int64_t lx = (int64_t)s->mesh->nx * s->p + 1, ly = (int64_t)s->mesh->ny * s->p + 1,
+                lz = (int64_t)s->mesh->nz * s->p + 1;
+  return lx * ly * lz - (lx - 2) * (ly - 2) * (lz - 2);
+}
 
 int pafem_space_get_restriction(const pafem_space* s, int32_t* E_host) {
   clear_error();
   CHECK_ARG(s && E_host, "NULL argument");
+  PAFEM_TRY(ensure_host_maps(const_cast<pafem_space*>(s)));
   std::memcpy(E_host, s->E.data(), s->E.size() * sizeof(int32_t));
   return PAFEM_OK;
 }
@@ -322,6 +385,7 @@ int pafem_space_get_restriction(const pafem_space* s, int32_t* E_host) {
 int pafem_space_get_restriction_transpose(const pafem_space* s, int32_t* off, int32_t* idx) {
   clear_error();
   CHECK_ARG(s && off && idx, "NULL argument");
+  PAFEM_TRY(ensure_host_maps(const_cast<pafem_space*>(s)));
   std::memcpy(off, s->et_off.data(), s->et_off.size() * sizeof(int32_t));
   std::memcpy(idx, s->et_idx.data(), s->et_idx.size() * sizeof(int32_t));
   return PAFEM_OK;
@@ -330,6 +394,7 @@ int pafem_space_get_restriction_transpose(const pafem_space* s, int32_t* off, in
 int pafem_space_get_ess_dofs(const pafem_space* s, int32_t* out) {
   clear_error();
   CHECK_ARG(s && out, "NULL argument");
+  PAFEM_TRY(ensure_ess(const_cast<pafem_space*>(s), false));
   std::memcpy(out, s->ess.data(), s->ess.size() * sizeof(int32_t));
   return PAFEM_OK;
 }
@@ -559,10 +624,12 @@ int pafem_op_diagonal(pafem_op* op, double* d, int constrained, void* stream) {
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   hipStream_t s = S(stream);
   PAFEM_TRY(diagonal_impl(op, d, constrained, s));
-  if (constrained)
+  if (constrained) {
+    PAFEM_TRY(ensure_ess(op->space, true));
     PAFEM_TRY_HIP(launch_set_ess<double>(op->space->d_ess.as<int32_t>(),
                                          (int64_t)op->space->ess.size(), nullptr, 1.0, 0, d,
                                          nullptr, s));
+  }
   return PAFEM_OK;
 }
 
@@ -572,15 +639,11 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_q, double* b, void* stream)
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   Space* sp = op->space;
   const int n = sp->p + 1;
-  PAFEM_TRY(ensure_et(sp));
   PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
   GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, n), tabWts(op->d_tab64, op->q, n));
   hipStream_t s = S(stream);
   PAFEM_TRY_HIP(launch_rhs_elem(g, sp->p, tabB<double>(op->d_tab64), f_q, op->d_evec.as<double>(), s));
-  PAFEM_TRY_HIP(launch_gather_et<double>(op->d_evec.as<double>(), sp->d_et_off.as<int32_t>(),
-                                         sp->d_et_idx.as<int32_t>(), sp->d_ess_mask.as<uint8_t>(),
-                                         1, 0, nullptr, b, sp->ndofs, nullptr, s));
-  return PAFEM_OK;
+  return gather_full(op, op->d_evec.as<double>(), 1, b, s);
 }
 
 int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x, const double* y, double* result,

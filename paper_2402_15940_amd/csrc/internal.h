@@ -114,6 +114,11 @@ struct Space : RefCounted {
   Mesh* mesh = nullptr;
   int p = 0;
   int64_t ndofs = 0, ne = 0;
+  // Integer maps, built on first use: the kernels compute the lattice
+  // numbering themselves, so large meshes never pay for the stored maps
+  // unless a caller asks for them.
+  bool have_maps = false, have_dev_maps = false;  // E, E^T, essential mask
+  bool have_ess = false, have_dev_ess = false;    // essential list
   std::vector<int32_t> E, et_off, et_idx, ess;
   std::vector<uint8_t> ess_mask;
   DevBuf d_E, d_et_off, d_et_idx, d_ess, d_ess_mask;
@@ -160,7 +165,9 @@ struct Op : RefCounted {
 };
 
 // Shared host helpers (api.cpp).
-int ensure_et(Space* sp);
+int ensure_host_maps(Space* sp);
+int ensure_device_maps(Space* sp);
+int ensure_ess(Space* sp, bool device);
 template <typename T>
 int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s);
 int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s);
@@ -224,10 +231,11 @@ hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
                             T* y, int64_t ndofs, const int* skip, hipStream_t s);
 // The same sum with the E-vector positions of each dof computed from the
 // lattice (same ascending (e, l) order, so bitwise equal to the CSR form).
+// skip_interior: element-interior nodes were already stored by the element kernel.
 template <typename T>
 hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
-                                 int accumulate, const T* x, T* y, const int* skip,
-                                 hipStream_t s);
+                                 int accumulate, int skip_interior, const T* x, T* y,
+                                 const int* skip, hipStream_t s);
 
 // Essential-dof fix-up: y[ess[i]] (+)= x ? x[ess[i]] : value.
 template <typename T>

@@ -1,451 +1,36 @@
-// Fused partial-assembly operator kernels for gfx950: y = E^T B^T D B E x.
-//
-// Each element runs through five stages; every stage gives one thread one 1D
-// line of the element and the full 1D table, so the tables are wave-uniform
-// (scalar-register operands) and LDS carries each intermediate exactly once:
-//
-//   A   y contraction   line (a, c):   gather x_e(a, :, c)  -> B x, G x      (per qy)
-//   B   x contraction   line (qy, c):  -> (B,B) (G,B) (B,G) factors         (per qx)
-//   C   z contraction   line (qx, qy): -> reference gradient at every qz,
-//                                         pointwise D (6 stored factors),
-//                                         transposed z contraction
-//   B^T x contraction   line (qy, c)
-//   A^T y contraction   line (a, c):   -> y_e(a, :, c)  -> scatter (E^T)
-//
-// Lanes of stages A/A^T run along x, so the gather and the scatter-add touch
-// consecutive dofs; lanes of stage C run along qx, so the quadrature-data
-// stream is read in contiguous runs.
-//
-// LDS holds, per element, one private region of R words for every (c, qy)
-// pair; each stage reads its line's inputs from the regions it owns and
-// writes its outputs back into the same regions, so one buffer of N*Q*R words
-// serves every stage (R = max(2N, 3Q) rounded up to an odd count, which keeps
-// 64-bit LDS accesses with a line stride of R conflict-free).
-//
-// The element restriction E is either the stored int32 map or computed from
-// the lattice coordinates of the structured mesh (no index traffic, and the x
-// loads can be issued at kernel start together with the quadrature data).
-#include "internal.h"
+// Per-operator launches of the fused partial-assembly element kernels
+// (bodies in apply_impl.h) and their dispatch over p, precision, E^T mode and
+// restriction source.
+#include "apply_impl.h"
 
 namespace pafem {
 
 namespace {
 
-constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+using apply::Cfg;
+using apply::xcd_block;
 
-// Launch tuning, measured on MI355X (overridable at build time for sweeps):
-// elements per workgroup by q, and the waves per SIMD the register allocation
-// must leave room for, by p, for the FP64 diffusion kernel.
-#ifndef PAFEM_NE_BY_Q
-#define PAFEM_NE_BY_Q 1, 1, 1, 7, 4, 5, 7, 5, 1, 3, 2
-#endif
-#ifndef PAFEM_WAVES_DIFF_F64
-#define PAFEM_WAVES_DIFF_F64 1, 1, 1, 1, 4, 1, 1, 1, 1
-#endif
-constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
-constexpr int kWavesDiff64[] = {PAFEM_WAVES_DIFF_F64};
-
-__host__ __device__ constexpr int odd_up(int v) { return (v % 2 == 0) ? v + 1 : v; }
-__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
-
-
-template <int P, int Q, typename T, int KIND>
-struct Cfg {
-  static constexpr int N = P + 1;
-  static constexpr int QQ = Q * Q;
-  static constexpr int R = KIND == PAFEM_DIFFUSION ? odd_up(cmax(2 * N, 3 * Q)) : odd_up(cmax(N, Q));
-  static constexpr int L = N * Q * R;  // LDS words per element
-  static constexpr int NE = kNeByQ[Q];
-  static constexpr int THREADS = ((NE * QQ + 63) / 64) * 64;
-  // waves per SIMD the register allocation must allow (occupancy floor)
-  static constexpr int MIN_WAVES =
-      (KIND == PAFEM_DIFFUSION && sizeof(T) == 8) ? kWavesDiff64[P] : 1;
-  static_assert(NE * L * (int)sizeof(T) <= 64 * 1024, "LDS budget");
-};
-
-// Workgroups are dealt to the XCDs round-robin; renumber them so that each XCD
-// works on one contiguous run of elements (neighbours share face dofs in the
-// XCD's L2 for both the x gather and the y scatter).
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  const int64_t x = b % kXcds, k = b / kXcds;
-  const int64_t q = nb / kXcds, r = nb % kXcds;
-  return x * q + (x < r ? x : r) + k;
-}
-
-// Element restriction E of one element: the stored map row, or the lattice
-// numbering of the structured mesh computed on the fly.
-template <int P, int IDX, typename T>
-struct Restrict {
-  const int32_t* Ee;
-  int I0, J0, K0;
-  int Lx, Ly, Lz;
-  __device__ __forceinline__ void init(const ApplyArgs<T>& a, int64_t e) {
-    constexpr int N = P + 1;
-    Lx = a.nx * P + 1;
-    Ly = a.ny * P + 1;
-    Lz = a.nz * P + 1;
-    if (IDX == PAFEM_INDEX_MAP) {
-      Ee = a.E + e * (N * N * N);
-    } else {
-      const int64_t t = e / a.nx;
-      I0 = (int)(e - t * a.nx) * P;
-      J0 = (int)(t % a.ny) * P;
-      K0 = (int)(t / a.ny) * P;
-    }
-  }
-  __device__ __forceinline__ int32_t dof(int aa, int b, int c) const {
-    constexpr int N = P + 1;
-    if (IDX == PAFEM_INDEX_MAP) return Ee[(c * N + b) * N + aa];
-    return (I0 + aa) + Lx * ((J0 + b) + Ly * (K0 + c));
-  }
-  __device__ __forceinline__ bool ess(const ApplyArgs<T>& a, int32_t g, int aa, int b,
-                                      int c) const {
-    if (IDX == PAFEM_INDEX_MAP) return a.ess_mask[g] != 0;
-    const int I = I0 + aa, J = J0 + b, K = K0 + c;
-    return I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1;
-  }
-};
-
-template <typename T>
-__device__ __forceinline__ void scatter_add(T* p, T v) {
-  atomicAdd(p, v);
-}
-
-// Where one element result goes:
-//   atomic         global FP64/FP32 atomic add into y (memory-side on MI355X);
-//   deterministic  element-interior nodes (owned by this element alone) are
-//                  stored to y directly when E is the lattice numbering; every
-//                  other node goes to the E-vector for the ordered per-dof sum;
-//   E-vector       every node goes to the E-vector.
-template <int P, int SCATTER, int IDX, typename T>
-__device__ __forceinline__ void store_result(const ApplyArgs<T>& a, const Restrict<P, IDX, T>& E,
-                                             int64_t e, int aa, int b, int c, bool interior,
-                                             T acc) {
-  constexpr int N = P + 1;
-  if (SCATTER == kScatterEvector ||
-      (SCATTER == PAFEM_SCATTER_DETERMINISTIC && (IDX == PAFEM_INDEX_MAP || !interior))) {
-    a.yE[e * (N * N * N) + (c * N + b) * N + aa] = acc;
-  } else if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
-    const int32_t g = E.dof(aa, b, c);
-    a.y[g] = a.accumulate ? a.y[g] + acc : acc;
-  } else {
-    const int32_t g = E.dof(aa, b, c);
-    if (!(a.constrained && E.ess(a, g, aa, b, c))) scatter_add(a.y + g, acc);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// diffusion: y_e = sum_ij G_i^T S_ij G_j x_e, S = w k adj(J) adj(J)^T / detJ
-// stored as the 6 upper-triangle entries per quadrature point.
-// ---------------------------------------------------------------------------
 template <int P, int Q, typename T, int SCATTER, int IDX>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
                              (Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES)) void k_apply_diff(
     ApplyArgs<T> a) {
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
-  constexpr int N = C::N, QQ = C::QQ, NE = C::NE, L = C::L, R = C::R;
-  constexpr int QQQ = Q * Q * Q;
-  __shared__ T smem[NE * L];
+  __shared__ T smem[C::NE * C::L];
   if (a.skip != nullptr && *a.skip) return;
-
-  const int tid = threadIdx.x;
-  const int64_t nb = (a.ne + NE - 1) / NE;
-  const int64_t e0 = xcd_block(blockIdx.x, nb) * NE;
-  const T* __restrict__ Bt = a.B;
-  const T* __restrict__ Gt = a.G;
-
-  // stage-C role of this thread: z-line (qx, qy) of element slot sC
-  const int sC = tid / QQ, rC = tid - sC * QQ;
-  const int64_t eC = e0 + sC;
-  const bool actC = sC < NE && eC < a.ne;
-  const int qxC = rC % Q, qyC = rC / Q;
-
-  // Quadrature data of this thread's z-line, issued first: the dominant HBM
-  // stream, consumed only in stage C.
-  T dq[6][Q];
-  if (actC) {
-    const T* qd = a.qd + eC * (6 * QQQ) + qyC * Q + qxC;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-      for (int qz = 0; qz < Q; ++qz) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
-  }
-
-  // stage-A role: y-line (a, c); lanes run along x so gather and scatter coalesce
-  const int sA = tid / (N * N), rA = tid - sA * (N * N);
-  const int64_t eA = e0 + sA;
-  const bool actA = sA < NE && eA < a.ne;
-  const int aA = rA % N, cA = rA / N;
-
-  // ---- stage A: gather + y contraction ----
-  if (actA) {
-    Restrict<P, IDX, T> E;
-    E.init(a, eA);
-    T u[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int32_t g = E.dof(aA, b, cA);
-      T v = a.x[g];
-      if (a.constrained && E.ess(a, g, aA, b, cA)) v = T(0);
-      u[b] = v;
-    }
-    T* reg = smem + sA * L + (cA * Q) * R + aA;  // region (c, qy) at + qy*R
-#pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-      T tb = 0, tg = 0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        tb += Bt[qy * N + b] * u[b];
-        tg += Gt[qy * N + b] * u[b];
-      }
-      reg[qy * R] = tb;
-      reg[qy * R + N] = tg;
-    }
-  }
-  __syncthreads();
-
-  // ---- stage B: x contraction, x-line (qy, c) ----
-  const int sB = tid / (Q * N), rB = tid - sB * (Q * N);
-  const bool actB = sB < NE && e0 + sB < a.ne;
-  const int qyB = rB % Q, cB = rB / Q;
-  if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qyB) * R;
-    T tb[N], tg[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      tb[i] = reg[i];
-      tg[i] = reg[N + i];
-    }
-#pragma unroll
-    for (int qx = 0; qx < Q; ++qx) {
-      T bb = 0, gb = 0, bg = 0;  // factors (x, y): (B,B) (G,B) (B,G)
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        bb += Bt[qx * N + i] * tb[i];
-        gb += Gt[qx * N + i] * tb[i];
-        bg += Bt[qx * N + i] * tg[i];
-      }
-      reg[qx] = bb;
-      reg[Q + qx] = gb;
-      reg[2 * Q + qx] = bg;
-    }
-  }
-  __syncthreads();
-
-  // ---- stage C: z contraction, pointwise D, transposed z contraction ----
-  if (actC) {
-    T* reg0 = smem + sC * L + qyC * R + qxC;  // + c*Q*R + k*Q
-    T ibb[N], igb[N], ibg[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      ibb[c] = reg0[c * Q * R];
-      igb[c] = reg0[c * Q * R + Q];
-      ibg[c] = reg0[c * Q * R + 2 * Q];
-    }
-    T w1[N], w2[N], w3[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) w1[c] = w2[c] = w3[c] = 0;
-#pragma unroll
-    for (int qz = 0; qz < Q; ++qz) {
-      T gx = 0, gy = 0, gz = 0;
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        gx += Bt[qz * N + c] * igb[c];
-        gy += Bt[qz * N + c] * ibg[c];
-        gz += Gt[qz * N + c] * ibb[c];
-      }
-      const T vx = dq[0][qz] * gx + dq[1][qz] * gy + dq[2][qz] * gz;
-      const T vy = dq[1][qz] * gx + dq[3][qz] * gy + dq[4][qz] * gz;
-      const T vz = dq[2][qz] * gx + dq[4][qz] * gy + dq[5][qz] * gz;
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        w1[c] += Bt[qz * N + c] * vx;
-        w2[c] += Bt[qz * N + c] * vy;
-        w3[c] += Gt[qz * N + c] * vz;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      reg0[c * Q * R] = w1[c];
-      reg0[c * Q * R + Q] = w2[c];
-      reg0[c * Q * R + 2 * Q] = w3[c];
-    }
-  }
-  __syncthreads();
-
-  // ---- stage B^T: transposed x contraction, x-line (qy, c) ----
-  // x-path needs G in x, the y- and z-paths B in x; afterwards the x- and
-  // z-paths share B in y, so they are summed here.
-  if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qyB) * R;
-    T w1[Q], w2[Q], w3[Q];
-#pragma unroll
-    for (int qx = 0; qx < Q; ++qx) {
-      w1[qx] = reg[qx];
-      w2[qx] = reg[Q + qx];
-      w3[qx] = reg[2 * Q + qx];
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s13 = 0, s2 = 0;
-#pragma unroll
-      for (int qx = 0; qx < Q; ++qx) {
-        s13 += Gt[qx * N + i] * w1[qx] + Bt[qx * N + i] * w3[qx];
-        s2 += Bt[qx * N + i] * w2[qx];
-      }
-      reg[i] = s13;
-      reg[N + i] = s2;
-    }
-  }
-  __syncthreads();
-
-  // ---- stage A^T: transposed y contraction + scatter, y-line (a, c) ----
-  if (actA) {
-    const T* reg = smem + sA * L + (cA * Q) * R + aA;
-    T X13[Q], X2[Q];
-#pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-      X13[qy] = reg[qy * R];
-      X2[qy] = reg[qy * R + N];
-    }
-    Restrict<P, IDX, T> E;
-    E.init(a, eA);
-    const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      T acc = 0;
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * X13[qy] + Gt[qy * N + b] * X2[qy];
-      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
-    }
-  }
+  const int64_t nb = (a.ne + C::NE - 1) / C::NE;
+  const int64_t e0 = xcd_block(blockIdx.x, nb) * C::NE;
+  apply::diff_elements<P, Q, T, SCATTER, IDX, C::NE>(a, e0, smem, threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// mass: y_e = B^T D B x_e with D = w rho detJ.
-// ---------------------------------------------------------------------------
 template <int P, int Q, typename T, int SCATTER, int IDX>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_mass(
     ApplyArgs<T> a) {
   using C = Cfg<P, Q, T, PAFEM_MASS>;
-  constexpr int N = C::N, QQ = C::QQ, NE = C::NE, L = C::L, R = C::R;
-  constexpr int QQQ = Q * Q * Q;
-  __shared__ T smem[NE * L];
+  __shared__ T smem[C::NE * C::L];
   if (a.skip != nullptr && *a.skip) return;
-
-  const int tid = threadIdx.x;
-  const int64_t nb = (a.ne + NE - 1) / NE;
-  const int64_t e0 = xcd_block(blockIdx.x, nb) * NE;
-  const T* __restrict__ Bt = a.B;
-
-  const int sC = tid / QQ, rC = tid - sC * QQ;
-  const int64_t eC = e0 + sC;
-  const bool actC = sC < NE && eC < a.ne;
-  const int qxC = rC % Q, qyC = rC / Q;
-  T dq[Q];
-  if (actC) {
-    const T* qd = a.qd + eC * QQQ + qyC * Q + qxC;
-#pragma unroll
-    for (int qz = 0; qz < Q; ++qz) dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
-  }
-
-  const int sA = tid / (N * N), rA = tid - sA * (N * N);
-  const int64_t eA = e0 + sA;
-  const bool actA = sA < NE && eA < a.ne;
-  const int aA = rA % N, cA = rA / N;
-  if (actA) {
-    Restrict<P, IDX, T> E;
-    E.init(a, eA);
-    T u[N];
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int32_t g = E.dof(aA, b, cA);
-      T v = a.x[g];
-      if (a.constrained && E.ess(a, g, aA, b, cA)) v = T(0);
-      u[b] = v;
-    }
-    T* reg = smem + sA * L + (cA * Q) * R + aA;
-#pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-      T tb = 0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) tb += Bt[qy * N + b] * u[b];
-      reg[qy * R] = tb;
-    }
-  }
-  __syncthreads();
-
-  const int sB = tid / (Q * N), rB = tid - sB * (Q * N);
-  const bool actB = sB < NE && e0 + sB < a.ne;
-  const int qyB = rB % Q, cB = rB / Q;
-  if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qyB) * R;
-    T tb[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) tb[i] = reg[i];
-#pragma unroll
-    for (int qx = 0; qx < Q; ++qx) {
-      T bb = 0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) bb += Bt[qx * N + i] * tb[i];
-      reg[qx] = bb;
-    }
-  }
-  __syncthreads();
-
-  if (actC) {
-    T* reg0 = smem + sC * L + qyC * R + qxC;
-    T in[N], w[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      in[c] = reg0[c * Q * R];
-      w[c] = 0;
-    }
-#pragma unroll
-    for (int qz = 0; qz < Q; ++qz) {
-      T uq = 0;
-#pragma unroll
-      for (int c = 0; c < N; ++c) uq += Bt[qz * N + c] * in[c];
-      const T v = dq[qz] * uq;
-#pragma unroll
-      for (int c = 0; c < N; ++c) w[c] += Bt[qz * N + c] * v;
-    }
-#pragma unroll
-    for (int c = 0; c < N; ++c) reg0[c * Q * R] = w[c];
-  }
-  __syncthreads();
-
-  if (actB) {
-    T* reg = smem + sB * L + (cB * Q + qyB) * R;
-    T w[Q];
-#pragma unroll
-    for (int qx = 0; qx < Q; ++qx) w[qx] = reg[qx];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s1 = 0;
-#pragma unroll
-      for (int qx = 0; qx < Q; ++qx) s1 += Bt[qx * N + i] * w[qx];
-      reg[i] = s1;
-    }
-  }
-  __syncthreads();
-
-  if (actA) {
-    const T* reg = smem + sA * L + (cA * Q) * R + aA;
-    T W[Q];
-#pragma unroll
-    for (int qy = 0; qy < Q; ++qy) W[qy] = reg[qy * R];
-    Restrict<P, IDX, T> E;
-    E.init(a, eA);
-    const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      T acc = 0;
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * W[qy];
-      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
-    }
-  }
+  const int64_t nb = (a.ne + C::NE - 1) / C::NE;
+  const int64_t e0 = xcd_block(blockIdx.x, nb) * C::NE;
+  apply::mass_elements<P, Q, T, SCATTER, IDX, C::NE>(a, e0, smem, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

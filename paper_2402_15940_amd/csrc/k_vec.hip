@@ -7,42 +7,18 @@
 // workgroup's wavefronts through LDS, and writes one partial; a one-workgroup
 // kernel then sums the partials in a fixed tree order.  CG scalars (alpha,
 // beta, residual norms) never leave the device.
-#include "internal.h"
+#include "vec_impl.h"
 
 namespace pafem {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWave = 64;
-constexpr int kMaxBlocks = 2048;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-// Sum over the workgroup of NV values per thread; results valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV]) {
-  __shared__ double s[NV][kThreads / kWave];
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double w = wave_sum(v[k]);
-    if (lane == 0) s[k][wid] = w;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double acc = 0;
-      for (int i = 0; i < kThreads / kWave; ++i) acc += s[k][i];
-      out[k] = acc;
-    }
-  }
-}
+using vec::kThreads;
+using vec::kWave;
+using vec::kMaxBlocks;
+using vec::block_sum;
+using vec::gather_lattice_node;
+using vec::final_sums;
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE,
@@ -66,58 +42,16 @@ __global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
-// Elements (and local index) containing lattice coordinate I along one
-// direction with n elements of order p: two at an interior element face.
-__device__ __forceinline__ int lattice_cands(int I, int n, int p, int (&e)[2], int (&l)[2]) {
-  if (I % p == 0 && I > 0 && I < n * p) {
-    e[0] = I / p - 1;
-    l[0] = p;
-    e[1] = I / p;
-    l[1] = 0;
-    return 2;
-  }
-  int ee = I / p;
-  if (ee > n - 1) ee = n - 1;
-  e[0] = ee;
-  l[0] = I - ee * p;
-  return 1;
-}
-
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict__ yE, int nx,
                                                              int ny, int nz, int p,
                                                              int constrained, int accumulate,
+                                                             int skip_interior,
                                                              const T* __restrict__ x,
                                                              T* __restrict__ y, const int* skip) {
   if (skip != nullptr && *skip) return;
-  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Lx * Ly * Lz) return;
-  const int I = (int)(i % Lx);
-  const int J = (int)((i / Lx) % Ly);
-  const int K = (int)(i / (Lx * Ly));
-  // element-interior nodes were stored directly by the element kernel
-  if (I % p != 0 && J % p != 0 && K % p != 0) return;
-  T acc = 0;
-  const bool ess = I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1;
-  if (constrained && ess) {
-    acc = x ? x[i] : T(0);
-  } else {
-    const int n = p + 1;
-    const int64_t nloc = (int64_t)n * n * n;
-    int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
-    const int cx = lattice_cands(I, nx, p, ex, lx);
-    const int cy = lattice_cands(J, ny, p, ey, ly);
-    const int cz = lattice_cands(K, nz, p, ez, lz);
-    // ascending element number: z outermost, x innermost
-    for (int kz = 0; kz < cz; ++kz)
-      for (int ky = 0; ky < cy; ++ky)
-        for (int kx = 0; kx < cx; ++kx) {
-          const int64_t e = ex[kx] + (int64_t)nx * (ey[ky] + (int64_t)ny * ez[kz]);
-          acc += yE[e * nloc + lx[kx] + n * (ly[ky] + n * lz[kz])];
-        }
-  }
-  y[i] = accumulate ? y[i] + acc : acc;
+  gather_lattice_node<T>(yE, nx, ny, nz, p, constrained, accumulate, skip_interior, x, y, i);
 }
 
 template <typename T>
@@ -154,25 +88,6 @@ __global__ __launch_bounds__(kThreads) void k_dot_partial(const T* __restrict__ 
     v[0] += (double)x[i] * (double)y[i];
   block_sum<1>(v, out);
   if (threadIdx.x == 0) partials[blockIdx.x] = out[0];
-}
-
-// Sum `ncols` interleaved columns of partials[nb][ncols] in fixed order.
-__device__ __forceinline__ void final_sums(const double* partials, int nb, int ncols,
-                                           double* out) {
-  __shared__ double s[4][kThreads];
-  for (int c = 0; c < ncols; ++c) {
-    double acc = 0;
-    for (int i = threadIdx.x; i < nb; i += kThreads) acc += partials[i * ncols + c];
-    s[c][threadIdx.x] = acc;
-  }
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int c = 0; c < ncols; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0)
-    for (int c = 0; c < ncols; ++c) out[c] = s[c][0];
 }
 
 __global__ __launch_bounds__(kThreads) void k_sum_final(const double* __restrict__ partials,
@@ -364,16 +279,16 @@ template hipError_t launch_gather_et<float>(const float*, const int32_t*, const 
 
 template <typename T>
 hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
-                                 int accumulate, const T* x, T* y, const int* skip,
-                                 hipStream_t s) {
+                                 int accumulate, int skip_interior, const T* x, T* y,
+                                 const int* skip, hipStream_t s) {
   const int64_t n = ((int64_t)nx * p + 1) * ((int64_t)ny * p + 1) * ((int64_t)nz * p + 1);
   hipLaunchKernelGGL((k_gather_lattice<T>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     s, yE, nx, ny, nz, p, constrained, accumulate, x, y, skip);
+                     s, yE, nx, ny, nz, p, constrained, accumulate, skip_interior, x, y, skip);
   return hipGetLastError();
 }
-template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int,
+template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int, int,
                                                   const double*, double*, const int*, hipStream_t);
-template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int,
+template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int, int,
                                                  const float*, float*, const int*, hipStream_t);
 
 template <typename T>

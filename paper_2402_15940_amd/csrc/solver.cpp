@@ -91,6 +91,7 @@ int ensure_dinv(Op* op, hipStream_t s, bool want32) {
     PAFEM_TRY(op->d_dinv32.ensure(n * sizeof(float)));
     double* d = op->d_dinv64.as<double>();
     PAFEM_TRY(diagonal_impl(op, d, 1, s));
+    PAFEM_TRY(ensure_ess(sp, true));
     PAFEM_TRY_HIP(launch_set_ess<double>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), nullptr,
                                          1.0, 0, d, nullptr, s));
     PAFEM_TRY_HIP(launch_recip(d, d, op->d_dinv32.as<float>(), n, s));

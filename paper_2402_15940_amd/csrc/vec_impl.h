@@ -1,0 +1,115 @@
+// Device helpers shared by the vector kernels and the batched serving kernels:
+// wavefront/workgroup reductions and the lattice E^T sum at one node.
+#pragma once
+
+#include "internal.h"
+
+namespace pafem {
+namespace vec {
+
+constexpr int kThreads = 256;
+constexpr int kWave = 64;
+constexpr int kMaxBlocks = 2048;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the workgroup of NV values per thread; results valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (&out)[NV]) {
+  __shared__ double s[NV][kThreads / kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double w = wave_sum(v[k]);
+    if (lane == 0) s[k][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double acc = 0;
+      for (int i = 0; i < kThreads / kWave; ++i) acc += s[k][i];
+      out[k] = acc;
+    }
+  }
+}
+
+// Elements (and local index) containing lattice coordinate I along one
+// direction with n elements of order p: two at an interior element face.
+__device__ __forceinline__ int lattice_cands(int I, int n, int p, int (&e)[2], int (&l)[2]) {
+  if (I % p == 0 && I > 0 && I < n * p) {
+    e[0] = I / p - 1;
+    l[0] = p;
+    e[1] = I / p;
+    l[1] = 0;
+    return 2;
+  }
+  int ee = I / p;
+  if (ee > n - 1) ee = n - 1;
+  e[0] = ee;
+  l[0] = I - ee * p;
+  return 1;
+}
+
+// Sum `ncols` interleaved columns of partials[nb][ncols] in fixed order.
+__device__ __forceinline__ void final_sums(const double* partials, int nb, int ncols,
+                                           double* out) {
+  __shared__ double s[4][kThreads];
+  for (int c = 0; c < ncols; ++c) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) acc += partials[i * ncols + c];
+    s[c][threadIdx.x] = acc;
+  }
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < ncols; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < ncols; ++c) out[c] = s[c][0];
+}
+
+// E^T at lattice node i: the sum of its element contributions in ascending
+// (element, local node) order; constrained essential rows take x[i] (or 0).
+template <typename T>
+__device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, int nx, int ny,
+                                                    int nz, int p, int constrained,
+                                                    int accumulate, int skip_interior,
+                                                    const T* __restrict__ x, T* __restrict__ y,
+                                                    int64_t i) {
+  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
+  if (i >= Lx * Ly * Lz) return;
+  const int I = (int)(i % Lx);
+  const int J = (int)((i / Lx) % Ly);
+  const int K = (int)(i / (Lx * Ly));
+  // element-interior nodes were stored directly by the element kernel
+  if (skip_interior && I % p != 0 && J % p != 0 && K % p != 0) return;
+  T acc = 0;
+  const bool ess = I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1;
+  if (constrained && ess) {
+    acc = x ? x[i] : T(0);
+  } else {
+    const int n = p + 1;
+    const int64_t nloc = (int64_t)n * n * n;
+    int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
+    const int cx = lattice_cands(I, nx, p, ex, lx);
+    const int cy = lattice_cands(J, ny, p, ey, ly);
+    const int cz = lattice_cands(K, nz, p, ez, lz);
+    // ascending element number: z outermost, x innermost
+    for (int kz = 0; kz < cz; ++kz)
+      for (int ky = 0; ky < cy; ++ky)
+        for (int kx = 0; kx < cx; ++kx) {
+          const int64_t e = ex[kx] + (int64_t)nx * (ey[ky] + (int64_t)ny * ez[kz]);
+          acc += yE[e * nloc + lx[kx] + n * (ly[ky] + n * lz[kz])];
+        }
+  }
+  y[i] = accumulate ? y[i] + acc : acc;
+}
+
+}  // namespace vec
+}  // namespace pafem
