@@ -229,6 +229,86 @@ int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem
 int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x_dev, const double* y_dev,
               double* result_dev, void* stream);
 
+/* ---- serving: continuous batching of Poisson solves --------------------------- */
+/* A server owns one engine thread on the context's GPU.  Submitted requests
+ * (each a Dirichlet Poisson problem -div(k grad u) = f, f = 3 pi^2
+ * sin(pi x) sin(pi y) sin(pi z), on its own structured mesh and order) are
+ * admitted first-in first-out while a slot is free and their estimated
+ * device footprint fits the HBM budget; admitted requests keep their
+ * quadrature data resident, and all of them advance together: each round
+ * replays one HIP graph holding `iters_per_round` CG iterations whose kernels
+ * (the element pass over every active request's elements, whatever its
+ * order, then the E^T sums, reductions and vector updates) each cover the
+ * whole batch.  Requests finish independently; their memory returns to the
+ * budget at once and waiting requests are admitted in the next round.
+ * Results are bitwise independent of which other requests share the batch.
+ * IR_FP32 requests run their inner solves in the FP32 batch and their FP64
+ * refinement steps between rounds. */
+#define PAFEM_REQ_QUEUED 0
+#define PAFEM_REQ_RUNNING 1
+#define PAFEM_REQ_DONE 2
+#define PAFEM_REQ_FAILED 3
+
+#define PAFEM_COEF_CONST 0 /* k = coef_value */
+#define PAFEM_COEF_SINX 1  /* k = 1 + coef_value sin(2 pi x) */
+
+typedef struct pafem_server pafem_server;
+
+typedef struct {
+  int nx, ny, nz;           /* element lattice, each >= 1 */
+  int p;                    /* order 1..8 (q = p + 2) */
+  const double* verts_host; /* [(nx+1)(ny+1)(nz+1)][3], copied by pafem_server_submit */
+  int coef_kind;            /* PAFEM_COEF_CONST or PAFEM_COEF_SINX */
+  double coef_value;
+  int mode;                 /* PAFEM_SOLVE_PLAIN_FP64 or PAFEM_SOLVE_IR_FP32 */
+  double rtol;              /* relative residual target (FP64) */
+  double inner_rtol;        /* IR: inner FP32 relative tolerance */
+  int maxit;                /* CG iteration limit (per inner solve for IR) */
+  int max_outer;            /* IR: refinement step limit */
+} pafem_request;
+
+typedef struct {
+  int status;               /* PAFEM_REQ_* */
+  int error;                /* PAFEM_ERR_* when status is FAILED (NOT_CONVERGED keeps x) */
+  int64_t ndofs;
+  int64_t footprint_bytes;  /* device bytes reserved while admitted */
+  int iterations;           /* CG iterations (inner total for IR) */
+  int outer_iterations;
+  double rel_res;           /* final ||b - A x|| / ||b|| in FP64 */
+  double t_arrive, t_admit, t_done; /* seconds on the server clock (-1 if not yet) */
+} pafem_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, rounds;
+  int64_t peak_bytes;       /* largest sum of admitted footprints */
+  int max_active;           /* most requests admitted at once */
+  double dof_iterations;    /* sum over finished requests of ndofs * iterations */
+  double seconds;           /* server clock now */
+} pafem_server_counters;
+
+/* Device bytes a request reserves while admitted (quadrature data, E-vector,
+ * vectors, geometry), or -1 for an invalid request. */
+int64_t pafem_request_footprint(const pafem_request* req);
+
+/* Start a server on a GPU context with an HBM budget (bytes), at most
+ * max_slots requests admitted at once (1..64) and iters_per_round CG
+ * iterations per replayed graph (>= 1). */
+int pafem_server_create(pafem_ctx* ctx, int64_t hbm_budget_bytes, int max_slots,
+                        int iters_per_round, pafem_server** out);
+/* Queue a request (thread-safe, returns at once).  INVALID_ARG for a
+ * malformed request; a request larger than the whole budget is accepted and
+ * then fails with OUT_OF_MEMORY. */
+int pafem_server_submit(pafem_server* srv, const pafem_request* req, uint64_t* ticket);
+int pafem_server_poll(pafem_server* srv, uint64_t ticket, pafem_result* out);
+/* Copy the solution (ndofs doubles) of a finished request to x_host and
+ * release it.  INVALID_ARG if the request has not finished or n differs. */
+int pafem_server_get_solution(pafem_server* srv, uint64_t ticket, double* x_host, int64_t n);
+/* Block until every request submitted so far has finished. */
+int pafem_server_drain(pafem_server* srv);
+int pafem_server_stats(pafem_server* srv, pafem_server_counters* out);
+/* Drain, stop the engine and free everything. */
+int pafem_server_destroy(pafem_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

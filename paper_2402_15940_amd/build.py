@@ -16,7 +16,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libpafem.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-SOURCES = ["host_setup.cpp", "api.cpp", "solver.cpp", "k_setup.hip", "k_apply.hip", "k_vec.hip"]
+SOURCES = ["host_setup.cpp", "api.cpp", "solver.cpp", "server.cpp", "k_setup.hip", "k_apply.hip",
+           "k_vec.hip", "k_batched.hip"]
 
 ARCH = os.environ.get("PAFEM_ARCH", "gfx950")
 

@@ -215,10 +215,6 @@ template int apply_impl<float>(Op*, const float*, float*, int, const int*, hipSt
 
 using namespace pafem;
 
-struct pafem_ctx : Ctx {};
-struct pafem_mesh : Mesh {};
-struct pafem_space : Space {};
-struct pafem_op : Op {};
 
 namespace {
 

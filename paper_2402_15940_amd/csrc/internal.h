@@ -268,6 +268,47 @@ template <typename T>
 hipError_t launch_cg_pupdate(T* p, const T* r, const T* dinv, int64_t n, const CgState* st,
                              hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// batched kernels of the serving engine (k_batched.hip)
+// ---------------------------------------------------------------------------
+constexpr int kBatchThreads = 256;   // workgroup size of every batched kernel
+constexpr int kBatchChunk = 2048;    // dofs per vector chunk (8 per thread)
+
+// One active request of a batch: the CG vectors of one Poisson solve in
+// precision T and where its work items sit in the batch's index spaces.
+template <typename T>
+struct BatchEntry {
+  ApplyArgs<T> a;           // x = CG direction, y = A dir, yE = E-vector workspace
+  int p;
+  int nchunks;
+  int64_t ndofs;
+  int64_t work_begin, work_end;    // element work items [begin, end) of the batched apply
+  int64_t chunk_begin, chunk_end;  // vector chunks [begin, end)
+  T* x;
+  T* r;
+  T* dir;
+  T* Ad;
+  const T* dinv;
+  CgState* st;
+  double* partials;         // [nchunks][2]
+};
+
+struct BatchHeader {
+  int n;                    // active entries (sorted by work_begin / chunk_begin)
+  int pad;
+  int64_t total_work;
+  int64_t total_chunks;
+};
+
+// Elements per work item of the batched apply (q x q threads per element).
+__host__ __device__ constexpr int batch_elems(int q) { return kBatchThreads / (q * q); }
+
+// K CG iterations for every active entry of the batch; grids are fixed so the
+// sequence can be captured once and replayed while the membership changes.
+template <typename T>
+hipError_t launch_batch_iterations(const BatchEntry<T>* ents, const BatchHeader* hdr,
+                                   int max_entries, int iters, hipStream_t s);
+
 // Mixed-precision helpers.
 hipError_t launch_residual(const double* b, const double* Ax, double* r, int64_t n,
                            hipStream_t s);
@@ -278,4 +319,13 @@ hipError_t launch_axpy_from_f32(double* x, const double* norm2, const float* d32
 hipError_t launch_recip(const double* d, double* dinv64, float* dinv32, int64_t n,
                         hipStream_t s);
 
+// Solver helpers (solver.cpp).
+int ensure_dinv(Op* op, hipStream_t s, bool want32);
+
 }  // namespace pafem
+
+// The C handles are the library objects themselves.
+struct pafem_ctx : pafem::Ctx {};
+struct pafem_mesh : pafem::Mesh {};
+struct pafem_space : pafem::Space {};
+struct pafem_op : pafem::Op {};

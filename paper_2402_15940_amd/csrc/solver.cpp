@@ -83,23 +83,6 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
   return PAFEM_OK;
 }
 
-int ensure_dinv(Op* op, hipStream_t s, bool want32) {
-  Space* sp = op->space;
-  const int64_t n = sp->ndofs;
-  if (!op->have_dinv || (want32 && !op->d_dinv32.ptr)) {
-    PAFEM_TRY(op->d_dinv64.ensure(n * sizeof(double)));
-    PAFEM_TRY(op->d_dinv32.ensure(n * sizeof(float)));
-    double* d = op->d_dinv64.as<double>();
-    PAFEM_TRY(diagonal_impl(op, d, 1, s));
-    PAFEM_TRY(ensure_ess(sp, true));
-    PAFEM_TRY_HIP(launch_set_ess<double>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), nullptr,
-                                         1.0, 0, d, nullptr, s));
-    PAFEM_TRY_HIP(launch_recip(d, d, op->d_dinv32.as<float>(), n, s));
-    op->have_dinv = true;
-  }
-  return PAFEM_OK;
-}
-
 // ||b - A x|| / ||b|| in FP64 (uses the vectors r and Ax as scratch).
 int true_residual(Op* op, const double* b, const double* x, double* Ax, double* r, double bb,
                   hipStream_t s, double& out) {
@@ -120,6 +103,23 @@ int true_residual(Op* op, const double* b, const double* x, double* Ax, double* 
 
 }  // namespace
 
+int ensure_dinv(Op* op, hipStream_t s, bool want32) {
+  Space* sp = op->space;
+  const int64_t n = sp->ndofs;
+  if (!op->have_dinv || (want32 && !op->d_dinv32.ptr)) {
+    PAFEM_TRY(op->d_dinv64.ensure(n * sizeof(double)));
+    PAFEM_TRY(op->d_dinv32.ensure(n * sizeof(float)));
+    double* d = op->d_dinv64.as<double>();
+    PAFEM_TRY(diagonal_impl(op, d, 1, s));
+    PAFEM_TRY(ensure_ess(sp, true));
+    PAFEM_TRY_HIP(launch_set_ess<double>(sp->d_ess.as<int32_t>(), (int64_t)sp->ess.size(), nullptr,
+                                         1.0, 0, d, nullptr, s));
+    PAFEM_TRY_HIP(launch_recip(d, d, op->d_dinv32.as<float>(), n, s));
+    op->have_dinv = true;
+  }
+  return PAFEM_OK;
+}
+
 }  // namespace pafem
 
 using namespace pafem;
@@ -128,7 +128,7 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
                               const pafem_solve_opts* o, pafem_solve_stats* stats,
                               void* stream) {
   clear_error();
-  Op* op = reinterpret_cast<Op*>(op_);
+  Op* op = op_;
   if (!op || !b || !x || !o || !stats) {
     set_error("NULL argument");
     return PAFEM_ERR_INVALID_ARG;

@@ -54,6 +54,35 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Request(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("p", C.c_int),
+                ("verts_host", C.c_void_p), ("coef_kind", C.c_int), ("coef_value", C.c_double),
+                ("mode", C.c_int), ("rtol", C.c_double), ("inner_rtol", C.c_double),
+                ("maxit", C.c_int), ("max_outer", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("error", C.c_int), ("ndofs", C.c_int64),
+                ("footprint_bytes", C.c_int64), ("iterations", C.c_int),
+                ("outer_iterations", C.c_int), ("rel_res", C.c_double),
+                ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("rounds", C.c_int64), ("peak_bytes", C.c_int64), ("max_active", C.c_int),
+                ("dof_iterations", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+COEF_CONST, COEF_SINX = 0, 1
+
 _P = C.c_void_p
 _I = C.c_int
 _I64 = C.c_int64
@@ -95,6 +124,14 @@ _SIGNATURES = {
     "pafem_rhs_assemble": (_I, [_P, _P, _P, _P]),
     "pafem_solve_cg": (_I, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveStats), _P]),
     "pafem_dot": (_I, [_P, _I64, _P, _P, _P, _P]),
+    "pafem_request_footprint": (_I64, [C.POINTER(Request)]),
+    "pafem_server_create": (_I, [_P, _I64, _I, _I, _PP]),
+    "pafem_server_submit": (_I, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "pafem_server_poll": (_I, [_P, C.c_uint64, C.POINTER(Result)]),
+    "pafem_server_get_solution": (_I, [_P, C.c_uint64, _P, _I64]),
+    "pafem_server_drain": (_I, [_P]),
+    "pafem_server_stats": (_I, [_P, C.POINTER(ServerStats)]),
+    "pafem_server_destroy": (_I, [_P]),
 }
 
 _lib = None
@@ -405,6 +442,71 @@ class Operator:
     def close(self):
         if getattr(self, "_h", None):
             lib().pafem_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_request(nx, ny, nz, p, verts, coef_kind=COEF_CONST, coef_value=1.0,
+                 mode=SOLVE_IR_FP32, rtol=1e-10, inner_rtol=1e-4, maxit=20000, max_outer=30):
+    """Request structure plus the vertex array it points to (keep both alive)."""
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    if v.shape != ((nx + 1) * (ny + 1) * (nz + 1), 3):
+        raise ValueError("verts has the wrong shape")
+    req = Request(nx, ny, nz, p, v.ctypes.data, coef_kind, coef_value, mode, rtol, inner_rtol,
+                  maxit, max_outer)
+    return req, v
+
+
+def request_footprint(nx, ny, nz, p, mode=SOLVE_IR_FP32) -> int:
+    dummy = np.zeros(((nx + 1) * (ny + 1) * (nz + 1), 3))
+    req, _ = make_request(nx, ny, nz, p, dummy, mode=mode)
+    return lib().pafem_request_footprint(C.byref(req))
+
+
+class Server:
+    """Continuous-batching Poisson solve server on one GPU (see include/pafem.h)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_slots: int = 16,
+                 iters_per_round: int = 10):
+        h = C.c_void_p()
+        _check(lib().pafem_server_create(ctx.handle, int(budget_bytes), max_slots,
+                                         iters_per_round, C.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def submit(self, nx, ny, nz, p, verts, **kw) -> int:
+        req, v = make_request(nx, ny, nz, p, verts, **kw)
+        t = C.c_uint64()
+        _check(lib().pafem_server_submit(self._h, C.byref(req), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        r = Result()
+        _check(lib().pafem_server_poll(self._h, ticket, C.byref(r)))
+        return r.as_dict()
+
+    def solution(self, ticket: int) -> np.ndarray:
+        n = self.poll(ticket)["ndofs"]
+        x = np.empty(n)
+        _check(lib().pafem_server_get_solution(self._h, ticket, _np_ptr(x), n))
+        return x
+
+    def drain(self):
+        _check(lib().pafem_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().pafem_server_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pafem_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -100,3 +100,17 @@ def test_handles_destroyed_in_any_order():
     assert sp.ndofs == 7 * 4 * 4
     np.testing.assert_array_equal(sp.restriction(), fem.element_restriction(2, 1, 1, 3))
     sp.close()
+
+
+def test_server_needs_gpu_and_footprint_is_consistent():
+    ctx = pafem.Context(-1)
+    with pytest.raises(pafem.PafemError) as ei:
+        pafem.Server(ctx, 1 << 30)
+    assert ei.value.name == "UNSUPPORTED"
+    # footprint: quadrature data dominates and grows with elements * q^3
+    f1 = pafem.request_footprint(8, 8, 8, 4, pafem.SOLVE_PLAIN_FP64)
+    f2 = pafem.request_footprint(16, 16, 16, 4, pafem.SOLVE_PLAIN_FP64)
+    fir = pafem.request_footprint(8, 8, 8, 4, pafem.SOLVE_IR_FP32)
+    qd = 8 ** 3 * 6 ** 3 * 6 * 8
+    assert qd < f1 < 2 * qd and 7.5 < f2 / f1 < 8.5
+    assert fir - f1 >= 8 ** 3 * 6 ** 3 * 6 * 4       # FP32 copy of the quadrature data
