@@ -25,6 +25,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # hardware FP64/FP32 global atomic adds instead of CAS loops
     "-munsafe-fp-atomics",
+    # multiply-adds are fused only where the source says fma(): every kernel
+    # variant then rounds identically (bitwise reproducible results)
+    "-ffp-contract=off",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

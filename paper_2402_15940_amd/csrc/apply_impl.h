@@ -195,8 +195,8 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       T tb = 0, tg = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        tb += Bt[qy * N + b] * u[b];
-        tg += Gt[qy * N + b] * u[b];
+        tb = fma(Bt[qy * N + b], u[b], tb);
+        tg = fma(Gt[qy * N + b], u[b], tg);
       }
       reg[qy * R] = tb;
       reg[qy * R + N] = tg;
@@ -221,9 +221,9 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       T bb = 0, gb = 0, bg = 0;  // factors (x, y): (B,B) (G,B) (B,G)
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        bb += Bt[qx * N + i] * tb[i];
-        gb += Gt[qx * N + i] * tb[i];
-        bg += Bt[qx * N + i] * tg[i];
+        bb = fma(Bt[qx * N + i], tb[i], bb);
+        gb = fma(Gt[qx * N + i], tb[i], gb);
+        bg = fma(Bt[qx * N + i], tg[i], bg);
       }
       reg[qx] = bb;
       reg[Q + qx] = gb;
@@ -250,18 +250,18 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       T gx = 0, gy = 0, gz = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        gx += Bt[qz * N + c] * igb[c];
-        gy += Bt[qz * N + c] * ibg[c];
-        gz += Gt[qz * N + c] * ibb[c];
+        gx = fma(Bt[qz * N + c], igb[c], gx);
+        gy = fma(Bt[qz * N + c], ibg[c], gy);
+        gz = fma(Gt[qz * N + c], ibb[c], gz);
       }
-      const T vx = dq[0][qz] * gx + dq[1][qz] * gy + dq[2][qz] * gz;
-      const T vy = dq[1][qz] * gx + dq[3][qz] * gy + dq[4][qz] * gz;
-      const T vz = dq[2][qz] * gx + dq[4][qz] * gy + dq[5][qz] * gz;
+      const T vx = fma(dq[0][qz], gx, fma(dq[1][qz], gy, dq[2][qz] * gz));
+      const T vy = fma(dq[1][qz], gx, fma(dq[3][qz], gy, dq[4][qz] * gz));
+      const T vz = fma(dq[2][qz], gx, fma(dq[4][qz], gy, dq[5][qz] * gz));
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        w1[c] += Bt[qz * N + c] * vx;
-        w2[c] += Bt[qz * N + c] * vy;
-        w3[c] += Gt[qz * N + c] * vz;
+        w1[c] = fma(Bt[qz * N + c], vx, w1[c]);
+        w2[c] = fma(Bt[qz * N + c], vy, w2[c]);
+        w3[c] = fma(Gt[qz * N + c], vz, w3[c]);
       }
     }
 #pragma unroll
@@ -290,8 +290,8 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       T s13 = 0, s2 = 0;
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
-        s13 += Gt[qx * N + i] * w1[qx] + Bt[qx * N + i] * w3[qx];
-        s2 += Bt[qx * N + i] * w2[qx];
+        s13 = fma(Gt[qx * N + i], w1[qx], fma(Bt[qx * N + i], w3[qx], s13));
+        s2 = fma(Bt[qx * N + i], w2[qx], s2);
       }
       reg[i] = s13;
       reg[N + i] = s2;
@@ -315,7 +315,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int b = 0; b < N; ++b) {
       T acc = 0;
 #pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * X13[qy] + Gt[qy * N + b] * X2[qy];
+      for (int qy = 0; qy < Q; ++qy) acc = fma(Bt[qy * N + b], X13[qy], fma(Gt[qy * N + b], X2[qy], acc));
       store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
     }
   }
@@ -363,7 +363,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int qy = 0; qy < Q; ++qy) {
       T tb = 0;
 #pragma unroll
-      for (int b = 0; b < N; ++b) tb += Bt[qy * N + b] * u[b];
+      for (int b = 0; b < N; ++b) tb = fma(Bt[qy * N + b], u[b], tb);
       reg[qy * R] = tb;
     }
   }
@@ -381,7 +381,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int qx = 0; qx < Q; ++qx) {
       T bb = 0;
 #pragma unroll
-      for (int i = 0; i < N; ++i) bb += Bt[qx * N + i] * tb[i];
+      for (int i = 0; i < N; ++i) bb = fma(Bt[qx * N + i], tb[i], bb);
       reg[qx] = bb;
     }
   }
@@ -399,10 +399,10 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int qz = 0; qz < Q; ++qz) {
       T uq = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) uq += Bt[qz * N + c] * in[c];
+      for (int c = 0; c < N; ++c) uq = fma(Bt[qz * N + c], in[c], uq);
       const T v = dq[qz] * uq;
 #pragma unroll
-      for (int c = 0; c < N; ++c) w[c] += Bt[qz * N + c] * v;
+      for (int c = 0; c < N; ++c) w[c] = fma(Bt[qz * N + c], v, w[c]);
     }
 #pragma unroll
     for (int c = 0; c < N; ++c) reg0[c * Q * R] = w[c];
@@ -418,7 +418,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int i = 0; i < N; ++i) {
       T s1 = 0;
 #pragma unroll
-      for (int qx = 0; qx < Q; ++qx) s1 += Bt[qx * N + i] * w[qx];
+      for (int qx = 0; qx < Q; ++qx) s1 = fma(Bt[qx * N + i], w[qx], s1);
       reg[i] = s1;
     }
   }
@@ -436,7 +436,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int b = 0; b < N; ++b) {
       T acc = 0;
 #pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc += Bt[qy * N + b] * W[qy];
+      for (int qy = 0; qy < Q; ++qy) acc = fma(Bt[qy * N + b], W[qy], acc);
       store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
     }
   }
