@@ -595,6 +595,7 @@ int pafem_op_apply_evector(pafem_op* op, int prec, const void* x, void* yE, int 
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   Space* sp = op->space;
   hipStream_t s = S(stream);
+  if (op->index_mode == PAFEM_INDEX_MAP) PAFEM_TRY(ensure_device_maps(sp));
   if (prec == PAFEM_FP64) {
     CHECK_ARG(op->have64, "operator not assembled");
     ApplyArgs<double> a = make_args<double>(op, (const double*)x, nullptr, (double*)yE, flags,

@@ -73,6 +73,13 @@ template <typename T>
 hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode,
                         const ApplyArgs<T>& a, hipStream_t s) {
   if (q != p + 2) return hipErrorInvalidValue;
+  // the stored maps must be on the device before a kernel may read them
+  if (index_mode == PAFEM_INDEX_MAP && (a.E == nullptr || a.ess_mask == nullptr))
+    return hipErrorInvalidValue;
+  if (a.x == nullptr || a.qd == nullptr || a.B == nullptr || a.G == nullptr)
+    return hipErrorInvalidValue;
+  if (scatter_mode != PAFEM_SCATTER_ATOMIC && a.yE == nullptr) return hipErrorInvalidValue;
+  if (scatter_mode != kScatterEvector && a.y == nullptr) return hipErrorInvalidValue;
   switch (p) {
     case 1: return apply_p<1, T>(kind, scatter_mode, index_mode, a, s);
     case 2: return apply_p<2, T>(kind, scatter_mode, index_mode, a, s);
