@@ -20,7 +20,10 @@ The same JSON line also reports
     k = 1 + 0.5 sin 2 pi x), and p50/p99 latency of a small Poisson solve
     (4^3 affine mesh, p = 2);
   * sweep: FP64 diffusion/mass and FP32 diffusion apply GDOF/s for p = 1..8 at
-    about 8M dofs.
+    about 8M dofs;
+  * serving: a seeded Poisson-arrival stream of Poisson solves (N in 8..20,
+    p in 2..8) submitted in real time to the continuous-batching server, with
+    p50/p99 latency and aggregate GDOF/s per arrival rate.
 """
 from __future__ import annotations
 
@@ -145,6 +148,41 @@ def cpu_oracle_baseline(p, N, seconds_target=12.0):
                        f"not included")}
 
 
+def serve_benchmark(pf, ctx, rate, n_req, n_range, p_range, budget, max_slots, iters):
+    """Submit a seeded Poisson-arrival stream of Poisson solves in real time; report
+    p50/p99 latency (arrival to done, server clock) and aggregate GDOF/s."""
+    from paper_2402_15940_amd import inputs
+    stream = inputs.poisson_arrivals(n_req, rate, seed=15940, n_range=n_range, p_range=p_range)
+    verts = [inputs.perturbed_vertices(r["N"], r["N"], r["N"], seed=r["mesh_seed"]) for r in stream]
+    srv = pf.Server(ctx, budget, max_slots=max_slots, iters_per_round=iters)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, v in zip(stream, verts):
+        dt = r["t_arrive"] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        n = r["N"]
+        tickets.append(srv.submit(n, n, n, r["p"], v, mode=pf.SOLVE_IR_FP32, rtol=1e-10,
+                                  inner_rtol=1e-4, coef_kind=pf.COEF_CONST, coef_value=1.0))
+    srv.drain()
+    res = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    ok = [r for r in res if r["status"] == pf.REQ_DONE]
+    lat = np.array([r["t_done"] - r["t_arrive"] for r in ok]) * 1e3
+    t_first = min(r["t_arrive"] for r in res)
+    t_last = max(r["t_done"] for r in res)
+    dof_it = sum(r["ndofs"] * r["iterations"] for r in ok)
+    return {"rate_per_s": rate, "requests": n_req, "completed": len(ok),
+            "max_rel_res": max(r["rel_res"] for r in ok) if ok else None,
+            "p50_ms": round(float(np.percentile(lat, 50)), 2) if len(lat) else None,
+            "p99_ms": round(float(np.percentile(lat, 99)), 2) if len(lat) else None,
+            "aggregate_gdofs": round(dof_it / (t_last - t_first) / 1e9, 3),
+            "wall_s": round(t_last - t_first, 3), "max_active": st["max_active"],
+            "rounds": st["rounds"], "peak_gb": round(st["peak_bytes"] / 1e9, 3),
+            "mean_ndofs": int(np.mean([r["ndofs"] for r in res]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +193,10 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", type=str, default="2,8",
+                    help="arrival rates (requests/s) of the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--scatter", choices=["atomic", "deterministic"], default="deterministic")
     ap.add_argument("--copy-only", action="store_true",
                     help="stop after the headline applies and the copy reference (profiling runs)")
@@ -351,6 +393,20 @@ def main():
             del opp, spp, xx, yy, x32, y32
             torch.cuda.synchronize()
         extra["sweep_8M"] = sweep
+
+    # ---- serving: continuous batching of a Poisson-arrival stream ----------------------
+    if not args.no_serve:
+        serving = {"stream": ("N uniform in 8..20, p uniform in 2..8 (q=p+2), perturbed hex "
+                              "meshes, manufactured sine solution, FP32-inner/FP64-refined CG "
+                              "to rel. residual 1e-10; 64 GB budget, 16 slots, 10 iterations "
+                              "per round")}
+        runs = []
+        for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+            runs.append(serve_benchmark(pf, ctx, rate, args.serve_requests, (8, 20), (2, 8),
+                                        64 << 30, 16, 10))
+            log(f"serving {runs[-1]}")
+        serving["runs"] = runs
+        extra["serving"] = serving
 
     cpu = None
     if not args.no_cpu:
