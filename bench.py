@@ -61,7 +61,7 @@ def apply_flops(ne, n, q, kind):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("k_apply.hip", "internal.h"):
+    for f in ("k_apply.hip", "apply_impl.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2402_15940_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
