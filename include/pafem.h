@@ -65,6 +65,7 @@ extern "C" {
 
 #define PAFEM_FP64 1 /* vectors double, FP64 quadrature data and contractions */
 #define PAFEM_FP32 2 /* vectors float, FP32 quadrature data (rounded copy)     */
+#define PAFEM_BF16 4 /* vectors float, bfloat16 quadrature data, FP32 arithmetic */
 
 #define PAFEM_SCATTER_ATOMIC 0        /* E^T by global atomic adds (run-to-run rounding differences) */
 #define PAFEM_SCATTER_DETERMINISTIC 1 /* E^T by an E-vector and a per-dof sum in fixed (e, l) order:
@@ -78,6 +79,7 @@ extern "C" {
 
 #define PAFEM_SOLVE_PLAIN_FP64 0 /* Jacobi-PCG entirely in FP64 */
 #define PAFEM_SOLVE_IR_FP32 1    /* FP64 defect correction around an FP32 Jacobi-PCG */
+#define PAFEM_SOLVE_IR_BF16 2    /* the same with bfloat16 quadrature data in the inner operator */
 
 /* ---- opaque handles -------------------------------------------------------- */
 typedef struct pafem_ctx pafem_ctx;
@@ -154,7 +156,8 @@ int pafem_op_set_coefficient_sinx(pafem_op* op, double amp);
 /* Compute the quadrature data D on the device (synchronous).
  * MASS: D[e][0][qpt] = w rho detJ.  DIFFUSION: D[e][0..5][qpt] = the upper
  * triangle xx,xy,xz,yy,yz,zz of w k adj(J) adj(J)^T / detJ.  FP64 is always
- * built; prec_mask | PAFEM_FP32 also keeps an FP32 rounded copy.
+ * built; prec_mask | PAFEM_FP32 also keeps an FP32 rounded copy and
+ * prec_mask | PAFEM_BF16 a bfloat16 one (round to nearest even of the FP32 value).
  * INVALID_ARG if detJ <= 0 at any quadrature point (inverted element). */
 int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream);
 /* Device bytes the quadrature data occupies for prec_mask (or -1). */
@@ -170,8 +173,9 @@ int pafem_op_set_scatter_mode(pafem_op* op, int mode);
  * return).  Both give identical results. */
 int pafem_op_set_restriction_mode(pafem_op* op, int mode);
 
-/* y = A x.  prec selects double (PAFEM_FP64) or float (PAFEM_FP32, needs the
- * FP32 copy) vectors of length ndofs; x and y must not alias.  flags:
+/* y = A x.  prec selects double (PAFEM_FP64) or float vectors of length ndofs
+ * with the FP32 (PAFEM_FP32) or bfloat16 (PAFEM_BF16) quadrature data; the
+ * contractions then run in FP32.  x and y must not alias.  flags:
  *   0: the plain assembled operator;
  *   PAFEM_APPLY_CONSTRAINED: rows and columns of essential dofs replaced by
  *     the identity (y_ess = x_ess, free rows see x with essential entries 0);
@@ -199,7 +203,7 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_qpts_dev, double* b_dev, vo
 
 /* ---- solve ------------------------------------------------------------------- */
 typedef struct {
-  int mode;          /* PAFEM_SOLVE_PLAIN_FP64 or PAFEM_SOLVE_IR_FP32 */
+  int mode;          /* PAFEM_SOLVE_PLAIN_FP64, PAFEM_SOLVE_IR_FP32 or PAFEM_SOLVE_IR_BF16 */
   double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for plain CG) */
   double inner_rtol; /* IR: relative tolerance of each FP32 inner solve (e.g. 1e-4) */
   int maxit;         /* plain: max CG iterations; IR: max inner iterations per solve */
@@ -219,7 +223,8 @@ typedef struct {
  * Jacobi preconditioning; x_dev holds the initial guess on entry (its
  * essential entries must equal b's) and the solution on return.
  * Synchronous.  NOT_CONVERGED if the iteration limit is hit (x then holds the
- * last iterate and stats are filled).  IR_FP32 needs the FP32 quadrature copy. */
+ * last iterate and stats are filled).  IR_FP32 needs the FP32 quadrature copy,
+ * IR_BF16 the bfloat16 one. */
 int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem_solve_opts* opts,
                    pafem_solve_stats* stats, void* stream);
 

@@ -123,7 +123,8 @@ int ensure_ess(Space* sp, bool device) {
 }
 
 template <typename T>
-ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* skip) {
+ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* skip,
+                       int qprec = 0) {
   Space* sp = op->space;
   const int n = sp->p + 1;
   const DevBuf& tab = std::is_same<T, double>::value ? op->d_tab64 : op->d_tab32;
@@ -134,6 +135,9 @@ ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* sk
   a.E = sp->d_E.as<int32_t>();
   a.ess_mask = sp->d_ess_mask.as<uint8_t>();
   a.qd = std::is_same<T, double>::value ? (const T*)op->d_qd64.ptr : (const T*)op->d_qd32.ptr;
+  a.qd16 = (!std::is_same<T, double>::value && qprec == PAFEM_BF16) ? op->d_qd16.as<uint16_t>()
+                                                                    : nullptr;
+  if (a.qd16 != nullptr) a.qd = nullptr;
   a.B = tabB<T>(tab);
   a.G = tabG<T>(tab, op->q, n);
   a.ne = sp->ne;
@@ -147,7 +151,7 @@ ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* sk
 }
 
 template <typename T>
-int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s) {
+int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s, int qprec) {
   Space* sp = op->space;
   const int n = sp->p + 1;
   const int im = op->index_mode;
@@ -156,7 +160,7 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
     PAFEM_TRY(ensure_ess(sp, true));
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
     PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
-    ApplyArgs<T> a = make_args<T>(op, x, y, op->d_evec.as<T>(), flags, skip);
+    ApplyArgs<T> a = make_args<T>(op, x, y, op->d_evec.as<T>(), flags, skip, qprec);
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, im, a, s));
     if (im == PAFEM_INDEX_MAP) {
       PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(),
@@ -167,7 +171,7 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
                                              a.accumulate, 1, x, y, skip, s));
     }
   } else {
-    ApplyArgs<T> a = make_args<T>(op, x, y, nullptr, flags, skip);
+    ApplyArgs<T> a = make_args<T>(op, x, y, nullptr, flags, skip, qprec);
     // zero y with a kernel (not a memset) so the sequence can sit in a captured graph
     if (!a.accumulate) PAFEM_TRY_HIP(launch_fill<T>(y, sp->ndofs, T(0), skip, s));
     if (a.constrained)
@@ -208,8 +212,8 @@ int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
   return gather_full(op, op->d_evec.as<double>(), 0, d, s);
 }
 
-template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t);
-template int apply_impl<float>(Op*, const float*, float*, int, const int*, hipStream_t);
+template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t, int);
+template int apply_impl<float>(Op*, const float*, float*, int, const int*, hipStream_t, int);
 
 }  // namespace pafem
 
@@ -502,13 +506,14 @@ int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask) {
   const int64_t n = op->space->ne * (int64_t)op->q * op->q * op->q * op->ncomp;
   int64_t b = n * 8;
   if (prec_mask & PAFEM_FP32) b += n * 4;
+  if (prec_mask & PAFEM_BF16) b += n * 2;
   return b;
 }
 
 int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
   clear_error();
   CHECK_ARG(op, "NULL argument");
-  CHECK_ARG((prec_mask & ~(PAFEM_FP64 | PAFEM_FP32)) == 0, "unknown precision bits");
+  CHECK_ARG((prec_mask & ~(PAFEM_FP64 | PAFEM_FP32 | PAFEM_BF16)) == 0, "unknown precision bits");
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   const size_t n = (size_t)op->space->ne * op->q * op->q * op->q * op->ncomp;
   PAFEM_TRY(op->d_qd64.ensure(n * sizeof(double)));
@@ -517,20 +522,26 @@ int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
     PAFEM_TRY(op->d_qd32.ensure(n * sizeof(float)));
     q32 = op->d_qd32.as<float>();
   }
+  uint16_t* q16 = nullptr;
+  if (prec_mask & PAFEM_BF16) {
+    PAFEM_TRY(op->d_qd16.ensure(n * sizeof(uint16_t)));
+    q16 = op->d_qd16.as<uint16_t>();
+  }
   const int nn = op->space->p + 1;
   GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, nn), tabWts(op->d_tab64, op->q, nn));
   hipStream_t s = S(stream);
   PAFEM_TRY_HIP(hipMemsetAsync(op->d_flag.ptr, 0, sizeof(int), s));
   PAFEM_TRY_HIP(launch_qdata(g, op->kind, op->coef_kind, op->coef_value, op->d_coef.as<double>(),
-                             op->d_qd64.as<double>(), q32, op->d_flag.as<int>(), s));
+                             op->d_qd64.as<double>(), q32, q16, op->d_flag.as<int>(), s));
   int flag = 0;
   PAFEM_TRY_HIP(hipMemcpyAsync(&flag, op->d_flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
   PAFEM_TRY_HIP(hipStreamSynchronize(s));
   op->have64 = true;
   op->have32 = q32 != nullptr;
+  op->have16 = q16 != nullptr;
   op->have_dinv = false;
   if (flag) {
-    op->have64 = op->have32 = false;
+    op->have64 = op->have32 = op->have16 = false;
     set_error("non-positive Jacobian determinant at a quadrature point (inverted element)");
     return PAFEM_ERR_INVALID_ARG;
   }
@@ -540,13 +551,15 @@ int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
 int pafem_op_get_qdata(pafem_op* op, int prec, void* dst, void* stream) {
   clear_error();
   CHECK_ARG(op && dst, "NULL argument");
-  CHECK_ARG(prec == PAFEM_FP64 || prec == PAFEM_FP32, "prec must be FP64 or FP32");
-  const bool have = prec == PAFEM_FP64 ? op->have64 : op->have32;
+  CHECK_ARG(prec == PAFEM_FP64 || prec == PAFEM_FP32 || prec == PAFEM_BF16,
+            "prec must be FP64, FP32 or BF16");
+  const bool have = prec == PAFEM_FP64 ? op->have64 : prec == PAFEM_FP32 ? op->have32 : op->have16;
   CHECK_ARG(have, "quadrature data of that precision not assembled");
   const size_t n = (size_t)op->space->ne * op->q * op->q * op->q * op->ncomp;
-  const void* src = prec == PAFEM_FP64 ? op->d_qd64.ptr : op->d_qd32.ptr;
-  PAFEM_TRY_HIP(hipMemcpyAsync(dst, src, n * (prec == PAFEM_FP64 ? 8 : 4), hipMemcpyDeviceToDevice,
-                               S(stream)));
+  const void* src = prec == PAFEM_FP64 ? op->d_qd64.ptr
+                    : prec == PAFEM_FP32 ? op->d_qd32.ptr : op->d_qd16.ptr;
+  const size_t bytes = prec == PAFEM_FP64 ? 8 : prec == PAFEM_FP32 ? 4 : 2;
+  PAFEM_TRY_HIP(hipMemcpyAsync(dst, src, n * bytes, hipMemcpyDeviceToDevice, S(stream)));
   return PAFEM_OK;
 }
 
@@ -582,7 +595,12 @@ int pafem_op_apply(pafem_op* op, int prec, const void* x, void* y, int flags, vo
     CHECK_ARG(op->have32, "FP32 quadrature data not assembled");
     return apply_impl<float>(op, (const float*)x, (float*)y, flags, nullptr, S(stream));
   }
-  set_error("prec must be PAFEM_FP64 or PAFEM_FP32");
+  if (prec == PAFEM_BF16) {
+    CHECK_ARG(op->have16, "BF16 quadrature data not assembled");
+    return apply_impl<float>(op, (const float*)x, (float*)y, flags, nullptr, S(stream),
+                             PAFEM_BF16);
+  }
+  set_error("prec must be PAFEM_FP64, PAFEM_FP32 or PAFEM_BF16");
   return PAFEM_ERR_INVALID_ARG;
 }
 
@@ -603,9 +621,11 @@ int pafem_op_apply_evector(pafem_op* op, int prec, const void* x, void* yE, int 
     PAFEM_TRY_HIP(launch_apply<double>(op->kind, sp->p, op->q, kScatterEvector, op->index_mode, a, s));
     return PAFEM_OK;
   }
-  if (prec == PAFEM_FP32) {
-    CHECK_ARG(op->have32, "FP32 quadrature data not assembled");
-    ApplyArgs<float> a = make_args<float>(op, (const float*)x, nullptr, (float*)yE, flags, nullptr);
+  if (prec == PAFEM_FP32 || prec == PAFEM_BF16) {
+    CHECK_ARG(prec == PAFEM_FP32 ? op->have32 : op->have16,
+              "quadrature data of that precision not assembled");
+    ApplyArgs<float> a = make_args<float>(op, (const float*)x, nullptr, (float*)yE, flags, nullptr,
+                                          prec);
     PAFEM_TRY_HIP(launch_apply<float>(op->kind, sp->p, op->q, kScatterEvector, op->index_mode, a, s));
     return PAFEM_OK;
   }

@@ -111,6 +111,11 @@ struct Restrict {
   }
 };
 
+// bfloat16 bits (the upper half of an IEEE binary32) to float
+__device__ __forceinline__ float bf16_to_float(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
 template <typename T>
 __device__ __forceinline__ void scatter_add(T* p, T v) {
   atomicAdd(p, v);
@@ -164,11 +169,21 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   // stream, consumed only in stage C.
   T dq[6][Q];
   if (actC) {
-    const T* qd = a.qd + eC * (6 * QQQ) + qyC * Q + qxC;
+    const int64_t off = eC * (6 * QQQ) + qyC * Q + qxC;
+    if (a.qd16 != nullptr) {  // BF16 storage, FP32 arithmetic (wave-uniform branch)
+      const uint16_t* qd = a.qd16 + off;
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
+      for (int k = 0; k < 6; ++k)
 #pragma unroll
-      for (int qz = 0; qz < Q; ++qz) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
+        for (int qz = 0; qz < Q; ++qz)
+          dq[k][qz] = (T)bf16_to_float(__builtin_nontemporal_load(qd + k * QQQ + qz * QQ));
+    } else {
+      const T* qd = a.qd + off;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
+    }
   }
 
   // stage-A role: y-line (a, c); lanes run along x so gather and scatter coalesce
@@ -338,9 +353,16 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   const int qxC = rC % Q, qyC = rC / Q;
   T dq[Q];
   if (actC) {
-    const T* qd = a.qd + eC * QQQ + qyC * Q + qxC;
+    const int64_t off = eC * QQQ + qyC * Q + qxC;
+    if (a.qd16 != nullptr) {
+      const uint16_t* qd = a.qd16 + off;
 #pragma unroll
-    for (int qz = 0; qz < Q; ++qz) dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
+      for (int qz = 0; qz < Q; ++qz) dq[qz] = (T)bf16_to_float(__builtin_nontemporal_load(qd + qz * QQ));
+    } else {
+      const T* qd = a.qd + off;
+#pragma unroll
+      for (int qz = 0; qz < Q; ++qz) dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
+    }
   }
 
   const int sA = tid / (N * N), rA = tid - sA * (N * N);

@@ -150,8 +150,8 @@ struct Op : RefCounted {
   double coef_value = 1.0;
   DevBuf d_coef;                // [ne][q^3] when coef_kind == COEF_QPTS
   DevBuf d_tab64, d_tab32;      // B[q][n], G[q][n], pts[q], wts[q]
-  DevBuf d_qd64, d_qd32;        // quadrature data
-  bool have64 = false, have32 = false;
+  DevBuf d_qd64, d_qd32, d_qd16; // quadrature data (FP64, rounded FP32 and bfloat16 copies)
+  bool have64 = false, have32 = false, have16 = false;
   int scatter_mode = PAFEM_SCATTER_DETERMINISTIC;
   int index_mode = PAFEM_INDEX_LATTICE;
   DevBuf d_evec;                // E-vector workspace (deterministic scatter, diagonal, rhs)
@@ -168,8 +168,10 @@ struct Op : RefCounted {
 int ensure_host_maps(Space* sp);
 int ensure_device_maps(Space* sp);
 int ensure_ess(Space* sp, bool device);
+// qprec selects the stored quadrature data for float vectors: PAFEM_FP32 or PAFEM_BF16.
 template <typename T>
-int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s);
+int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s,
+               int qprec = 0);
 int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -186,8 +188,8 @@ struct GeomArgs {
 
 // Quadrature data (and optionally physical qpoint coordinates).
 hipError_t launch_qdata(const GeomArgs& g, int kind, int coef_kind, double coef_value,
-                        const double* coef_q, double* qd64, float* qd32, int* err_flag,
-                        hipStream_t s);
+                        const double* coef_q, double* qd64, float* qd32, uint16_t* qd16,
+                        int* err_flag, hipStream_t s);
 hipError_t launch_qpoint_coords(const GeomArgs& g, double* xyz, hipStream_t s);
 
 template <typename T>
@@ -198,6 +200,7 @@ struct ApplyArgs {
   const int32_t* E;
   const uint8_t* ess_mask;
   const T* qd;
+  const uint16_t* qd16;  // bfloat16 quadrature data instead of qd (float kernels), or null
   const T* B;         // [q][n]
   const T* G;         // [q][n]
   int64_t ne;

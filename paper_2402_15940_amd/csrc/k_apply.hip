@@ -76,7 +76,8 @@ hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode
   // the stored maps must be on the device before a kernel may read them
   if (index_mode == PAFEM_INDEX_MAP && (a.E == nullptr || a.ess_mask == nullptr))
     return hipErrorInvalidValue;
-  if (a.x == nullptr || a.qd == nullptr || a.B == nullptr || a.G == nullptr)
+  if (a.x == nullptr || (a.qd == nullptr && a.qd16 == nullptr) || a.B == nullptr ||
+      a.G == nullptr)
     return hipErrorInvalidValue;
   if (scatter_mode != PAFEM_SCATTER_ATOMIC && a.yE == nullptr) return hipErrorInvalidValue;
   if (scatter_mode != kScatterEvector && a.y == nullptr) return hipErrorInvalidValue;

@@ -23,6 +23,13 @@ __device__ __forceinline__ void qpoint_of(const GeomArgs& g, int64_t idx, int64_
   w = g.wts[qx] * g.wts[qy] * g.wts[qz];
 }
 
+// Round a (finite) float to the nearest bfloat16, ties to even.
+__device__ __forceinline__ uint16_t float_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 // MASS:       D = w rho detJ
 // DIFFUSION:  D = w k adj(J) adj(J)^T / detJ, upper triangle xx xy xz yy yz zz
 // adj(J) is the adjugate (transposed cofactor matrix), so adj(J)/detJ = J^-1.
@@ -31,6 +38,7 @@ __global__ __launch_bounds__(kThreads) void k_qdata(GeomArgs g, int kind, int co
                                                     const double* __restrict__ coef_q,
                                                     double* __restrict__ qd64,
                                                     float* __restrict__ qd32,
+                                                    uint16_t* __restrict__ qd16,
                                                     int* __restrict__ err_flag) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int qqq = g.q * g.q * g.q;
@@ -56,6 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_qdata(GeomArgs g, int kind, int co
     const double d = w * k * det;
     qd64[e * qqq + qp] = d;
     if (qd32) qd32[e * qqq + qp] = (float)d;
+    if (qd16) qd16[e * qqq + qp] = float_to_bf16((float)d);
     return;
   }
   // adjugate A = adj(J): A[i][j] = cofactor C[j][i]
@@ -79,6 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_qdata(GeomArgs g, int kind, int co
   for (int c = 0; c < 6; ++c) {
     qd64[base + (int64_t)c * qqq] = S[c];
     if (qd32) qd32[base + (int64_t)c * qqq] = (float)S[c];
+    if (qd16) qd16[base + (int64_t)c * qqq] = float_to_bf16((float)S[c]);
   }
 }
 
@@ -292,12 +302,12 @@ hipError_t rhs_p(const GeomArgs& g, const double* B, const double* f_q, double* 
 }  // namespace
 
 hipError_t launch_qdata(const GeomArgs& g, int kind, int coef_kind, double coef_value,
-                        const double* coef_q, double* qd64, float* qd32, int* err_flag,
-                        hipStream_t s) {
+                        const double* coef_q, double* qd64, float* qd32, uint16_t* qd16,
+                        int* err_flag, hipStream_t s) {
   const int64_t n = g.ne * g.q * g.q * g.q;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_qdata, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g, kind,
-                     coef_kind, coef_value, coef_q, qd64, qd32, err_flag);
+                     coef_kind, coef_value, coef_q, qd64, qd32, qd16, err_flag);
   return hipGetLastError();
 }
 

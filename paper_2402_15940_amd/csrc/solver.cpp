@@ -27,7 +27,8 @@ struct CgResult {
 // the initial guess unless x0_zero.  r, p, Ap are work vectors of length n.
 template <typename T>
 int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T* dinv,
-            double rtol, int maxit, int check_every, hipStream_t s, CgResult& res) {
+            double rtol, int maxit, int check_every, hipStream_t s, CgResult& res,
+            int qprec = 0) {
   Space* sp = op->space;
   const int64_t n = sp->ndofs;
   const int nb = reduce_blocks(n);
@@ -66,7 +67,7 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
   CgState hs{};
   for (;;) {
     for (int k = 0; k < check_every; ++k) {
-      PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s));
+      PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
       PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
       PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
       PAFEM_TRY_HIP(launch_cg_update<T>(x, r, p, Ap, dinv, n, part, nb, st, s));
@@ -137,11 +138,14 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     set_error("need rtol > 0, maxit >= 1, check_every >= 1");
     return PAFEM_ERR_INVALID_ARG;
   }
-  if (o->mode != PAFEM_SOLVE_PLAIN_FP64 && o->mode != PAFEM_SOLVE_IR_FP32) {
+  if (o->mode != PAFEM_SOLVE_PLAIN_FP64 && o->mode != PAFEM_SOLVE_IR_FP32 &&
+      o->mode != PAFEM_SOLVE_IR_BF16) {
     set_error("unknown solve mode");
     return PAFEM_ERR_INVALID_ARG;
   }
-  if (!op->have64 || (o->mode == PAFEM_SOLVE_IR_FP32 && !op->have32)) {
+  const bool ir = o->mode != PAFEM_SOLVE_PLAIN_FP64;
+  if (!op->have64 || (o->mode == PAFEM_SOLVE_IR_FP32 && !op->have32) ||
+      (o->mode == PAFEM_SOLVE_IR_BF16 && !op->have16)) {
     set_error("operator not assembled in the precision the mode needs");
     return PAFEM_ERR_INVALID_ARG;
   }
@@ -156,9 +160,9 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
   const int64_t n = sp->ndofs;
   *stats = pafem_solve_stats{};
 
-  PAFEM_TRY(ensure_dinv(op, s, o->mode == PAFEM_SOLVE_IR_FP32));
+  PAFEM_TRY(ensure_dinv(op, s, ir));
   // workspace: 3 FP64 vectors, plus 4 FP32 vectors for IR
-  const size_t need = 3 * n * sizeof(double) + (o->mode == PAFEM_SOLVE_IR_FP32 ? 4 * n * sizeof(float) : 0);
+  const size_t need = 3 * n * sizeof(double) + (ir ? 4 * n * sizeof(float) : 0);
   PAFEM_TRY(op->d_cg.ensure(need));
   double* r = op->d_cg.as<double>();
   double* p = r + n;
@@ -212,7 +216,8 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
       // the inner solve overwrites the partials; keep ||r||^2 in its own slot
       PAFEM_TRY(run_pcg<float>(op, r32, d32, true, r32, p32, Ap32, op->d_dinv32.as<float>(),
                                o->inner_rtol > 0 ? o->inner_rtol : 1e-4, o->maxit,
-                               o->check_every, s, res));
+                               o->check_every, s, res,
+                               o->mode == PAFEM_SOLVE_IR_BF16 ? PAFEM_BF16 : PAFEM_FP32));
       total_inner += res.iterations;
       PAFEM_TRY_HIP(launch_axpy_from_f32(x, rr_dev, d32, n, s));
       PAFEM_TRY(apply_impl<double>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));

@@ -21,6 +21,7 @@ MASS = 0
 DIFFUSION = 1
 FP64 = 1
 FP32 = 2
+BF16 = 4
 SCATTER_ATOMIC = 0
 SCATTER_DETERMINISTIC = 1
 INDEX_LATTICE = 0
@@ -29,6 +30,7 @@ APPLY_CONSTRAINED = 1
 APPLY_ACCUMULATE = 2
 SOLVE_PLAIN_FP64 = 0
 SOLVE_IR_FP32 = 1
+SOLVE_IR_BF16 = 2
 
 _ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "NOT_CONVERGED",
            -5: "UNSUPPORTED", -6: "NO_DEVICE"}
@@ -364,8 +366,9 @@ class Operator:
         return lib().pafem_op_qdata_bytes(self._h, prec_mask)
 
     def qdata(self, prec: int = FP64, stream=None):
+        """Stored quadrature data [ne, C, q^3]; the bfloat16 copy comes back as int16 bits."""
         torch = self._torch()
-        dt = torch.float64 if prec == FP64 else torch.float32
+        dt = {FP64: torch.float64, FP32: torch.float32, BF16: torch.int16}[prec]
         out = torch.empty(self.space.nelems * self.ncomp * self.q ** 3, dtype=dt, device="cuda")
         _check(lib().pafem_op_get_qdata(self._h, prec, _dptr(out), _stream(stream)))
         return out.view(self.space.nelems, self.ncomp, self.q ** 3)
@@ -377,9 +380,10 @@ class Operator:
         _check(lib().pafem_op_set_restriction_mode(self._h, mode))
 
     def apply(self, x, y=None, constrained: bool = False, accumulate: bool = False,
-              stream=None):
+              bf16: bool = False, stream=None):
+        """y = A x; float vectors use the FP32 quadrature data, or the bfloat16 copy."""
         torch = self._torch()
-        prec = FP64 if x.dtype == torch.float64 else FP32
+        prec = FP64 if x.dtype == torch.float64 else (BF16 if bf16 else FP32)
         n = self.space.ndofs
         if y is None:
             if accumulate:
@@ -390,10 +394,11 @@ class Operator:
                                     _dptr(y, x.dtype, n, "y"), flags, _stream(stream)))
         return y
 
-    def apply_evector(self, x, yE=None, constrained: bool = False, stream=None):
+    def apply_evector(self, x, yE=None, constrained: bool = False, bf16: bool = False,
+                      stream=None):
         """Element results before assembly, shape [nelems, (p+1)^3]."""
         torch = self._torch()
-        prec = FP64 if x.dtype == torch.float64 else FP32
+        prec = FP64 if x.dtype == torch.float64 else (BF16 if bf16 else FP32)
         m = self.space.nelems * (self.space.p + 1) ** 3
         if yE is None:
             yE = torch.empty(m, dtype=x.dtype, device=x.device)

@@ -467,3 +467,37 @@ def test_apply_evector_is_element_matrix_action(pf, ctx, kind, p):
             refc = Ae @ xt[E[e]]
             np.testing.assert_allclose(yEc[e], refc, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
             np.testing.assert_allclose(y32[e], ref, rtol=1e-4, atol=5e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("p", [2, 5, 7])
+def test_bf16_quadrature_data(pf, ctx, p):
+    """BF16 storage of D: every entry is the nearest bfloat16 of the FP32 copy, and the
+    FP32-arithmetic apply with it stays within the bfloat16 rounding of the operator."""
+    nx, ny, nz = 3, 2, 2
+    seed = inputs.mesh_seed(p, nx)
+    A = _oracle_matrix("diffusion", nx, ny, nz, p, seed, None)
+    v, op = _build(pf, ctx, "diffusion", nx, ny, nz, p, seed, prec=pf.FP64 | pf.FP32 | pf.BF16)
+    q32 = op.qdata(pf.FP32).cpu().numpy().ravel()
+    q16 = op.qdata(pf.BF16).cpu().numpy().ravel().astype(np.uint16)
+    back = (q16.astype(np.uint32) << 16).view(np.float32)
+    # nearest bfloat16: error at most half a unit in the 8-bit significand
+    assert np.all(np.abs(back - q32) <= np.abs(q32) * 2.0 ** -8 + 1e-45)
+    x = inputs.random_vector(op.space.ndofs, 2)
+    for mode, im in MODES(pf)[::3]:
+        op.set_scatter_mode(mode)
+        y = op.apply(torch.from_numpy(x).float().cuda(), bf16=True).double().cpu().numpy()
+        e2, _ = _relerr(y, A @ x)
+        assert 1e-6 < e2 <= 1e-2, e2
+
+
+def test_bf16_refined_solve_reaches_fp64_accuracy(pf, ctx):
+    n, p = 4, 4
+    v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
+    op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, v), p), pf.DIFFUSION)
+    op.set_coefficient_sinx(0.5)
+    op.assemble(pf.FP64 | pf.FP32 | pf.BF16)
+    b = op.rhs()
+    x64, s64 = op.solve(b, mode=pf.SOLVE_PLAIN_FP64, rtol=1e-12)
+    xb, sb = op.solve(b, mode=pf.SOLVE_IR_BF16, rtol=1e-10, inner_rtol=1e-3)
+    assert sb["true_rel_res"] <= 1e-10 and sb["outer_iterations"] >= 2
+    assert ((xb - x64).norm() / x64.norm()).item() < 1e-8
