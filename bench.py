@@ -194,9 +194,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", type=str, default="2,8",
+    ap.add_argument("--serve-rates", type=str, default="20,80,320",
                     help="arrival rates (requests/s) of the serving stream")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--scatter", choices=["atomic", "deterministic"], default="deterministic")
     ap.add_argument("--copy-only", action="store_true",
                     help="stop after the headline applies and the copy reference (profiling runs)")
@@ -217,7 +217,8 @@ def main():
     N = inputs.mesh_n_for_dofs(p, args.dofs)
     n, q = p + 1, p + 2
     log(f"headline: diffusion p={p} N={N}")
-    v, sp, ops = build_problem(pf, ctx, p, N, kinds=("diffusion", "mass"), prec=pf.FP64 | pf.FP32)
+    v, sp, ops = build_problem(pf, ctx, p, N, kinds=("diffusion", "mass"),
+                               prec=pf.FP64 | pf.FP32 | pf.BF16)
     K = ops["diffusion"]
     mode = pf.SCATTER_ATOMIC if args.scatter == "atomic" else pf.SCATTER_DETERMINISTIC
     for op in ops.values():
@@ -292,11 +293,21 @@ def main():
     x32 = x.float()
     y32 = torch.empty_like(x32)
     ms_f, msw_f = time_applies(torch, K, x32, y32, args.steps, 3)
+    for _ in range(3):
+        K.apply(x32, y32, bf16=True)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for _ in range(args.steps):
+        K.apply(x32, y32, bf16=True)
+    torch.cuda.synchronize()
+    msw_b = (time.perf_counter() - tb0) / args.steps * 1e3
     extra["apply"] = {
         "diffusion_fp64": {"ms": round(ms_wall, 5), "gdofs": round(value, 3),
                            "hbm_frac": round(apply_bytes(ne, n, q, 6, ndofs, 8) / (ms_wall * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "diffusion_fp32": {"ms": round(msw_f, 5), "gdofs": round(ndofs / (msw_f * 1e-3) / 1e9, 3),
                            "hbm_frac": round(apply_bytes(ne, n, q, 6, ndofs, 4) / (msw_f * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "diffusion_bf16_qdata": {"ms": round(msw_b, 5), "gdofs": round(ndofs / (msw_b * 1e-3) / 1e9, 3),
+                                 "hbm_frac": round((ne * q ** 3 * 12 + 8 * ndofs) / (msw_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "mass_fp64": {"ms": round(msw_m, 5), "gdofs": round(ndofs / (msw_m * 1e-3) / 1e9, 3),
                       "hbm_frac": round(apply_bytes(ne, n, q, 1, ndofs, 8) / (msw_m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
@@ -327,21 +338,24 @@ def main():
         # full solves to 1e-10 with the variable coefficient
         Kc = pf.Operator(sp, pf.DIFFUSION)
         Kc.set_coefficient_sinx(0.5)
-        Kc.assemble(pf.FP64 | pf.FP32)
+        Kc.assemble(pf.FP64 | pf.FP32 | pf.BF16)
         Kc.set_scatter_mode(mode)
         bc = Kc.rhs()
         solves = {}
-        for name, md in (("plain_fp64", pf.SOLVE_PLAIN_FP64), ("ir_fp32", pf.SOLVE_IR_FP32)):
+        for name, md in (("plain_fp64", pf.SOLVE_PLAIN_FP64), ("ir_fp32", pf.SOLVE_IR_FP32),
+                         ("ir_bf16", pf.SOLVE_IR_BF16)):
             xs = torch.zeros_like(bc)
             _, st = Kc.solve(bc, xs, mode=md, rtol=1e-10, inner_rtol=1e-4, maxit=20000,
                              check_every=25)
             solves[name] = {k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in st.items()}
             solves[name]["x"] = xs
-        d = (solves["ir_fp32"]["x"] - solves["plain_fp64"]["x"]).norm() / solves["plain_fp64"]["x"].norm()
+        x64 = solves["plain_fp64"]["x"]
+        for name in ("ir_fp32", "ir_bf16"):
+            solves[name]["rel_diff_vs_plain"] = float((solves[name]["x"] - x64).norm() / x64.norm())
+            solves[name]["speedup_vs_plain"] = round(solves["plain_fp64"]["seconds"] /
+                                                     solves[name]["seconds"], 3)
         for s_ in solves.values():
             s_.pop("x")
-        solves["ir_vs_plain_rel_diff"] = float(d)
-        solves["speedup_ir_over_plain"] = round(solves["plain_fp64"]["seconds"] / solves["ir_fp32"]["seconds"], 3)
         extra["solve_headline"] = solves
         log(f"solves {solves}")
         del Kc
