@@ -347,7 +347,8 @@ def main():
             xs = torch.zeros_like(bc)
             _, st = Kc.solve(bc, xs, mode=md, rtol=1e-10, inner_rtol=1e-4, maxit=20000,
                              check_every=25)
-            solves[name] = {k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in st.items()}
+            solves[name] = {k: (float(f"{v_:.4g}") if isinstance(v_, float) else v_)
+                            for k, v_ in st.items()}
             solves[name]["x"] = xs
         x64 = solves["plain_fp64"]["x"]
         for name in ("ir_fp32", "ir_bf16"):
