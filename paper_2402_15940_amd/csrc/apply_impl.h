@@ -323,16 +323,23 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       X13[qy] = reg[qy * R];
       X2[qy] = reg[qy * R + N];
     }
+    // the whole line is contracted before the first store: a global store
+    // may alias the tables as far as the compiler can tell, and would force
+    // every later table read onto the vector memory path
+    T acc[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      acc[b] = 0;
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy)
+        acc[b] = fma(Bt[qy * N + b], X13[qy], fma(Gt[qy * N + b], X2[qy], acc[b]));
+    }
     Restrict<P, IDX, T> E;
     E.init(a, eA);
     const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      T acc = 0;
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc = fma(Bt[qy * N + b], X13[qy], fma(Gt[qy * N + b], X2[qy], acc));
-      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
-    }
+    for (int b = 0; b < N; ++b)
+      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc[b]);
   }
 }
 
@@ -451,16 +458,19 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     T W[Q];
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) W[qy] = reg[qy * R];
+    T acc[N];  // contracted before the first store (see diff_elements)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      acc[b] = 0;
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy) acc[b] = fma(Bt[qy * N + b], W[qy], acc[b]);
+    }
     Restrict<P, IDX, T> E;
     E.init(a, eA);
     const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      T acc = 0;
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc = fma(Bt[qy * N + b], W[qy], acc);
-      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc);
-    }
+    for (int b = 0; b < N; ++b)
+      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc[b]);
   }
 }
 

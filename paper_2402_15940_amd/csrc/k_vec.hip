@@ -17,7 +17,6 @@ using vec::kThreads;
 using vec::kWave;
 using vec::kMaxBlocks;
 using vec::block_sum;
-using vec::gather_lattice_node;
 using vec::final_sums;
 
 template <typename T>
@@ -42,6 +41,10 @@ __global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
+// One workgroup per (slice of a) lattice row (J, K): a row that lies in an
+// element face plane (J or K a multiple of p) holds only surface nodes, every
+// other row only its x-face nodes I = f p once element-interior nodes are
+// skipped.  Index arithmetic stays 32-bit (lattice extents < 2^31).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict__ yE, int nx,
                                                              int ny, int nz, int p,
@@ -50,8 +53,16 @@ __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict
                                                              const T* __restrict__ x,
                                                              T* __restrict__ y, const int* skip) {
   if (skip != nullptr && *skip) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  gather_lattice_node<T>(yE, nx, ny, nz, p, constrained, accumulate, skip_interior, x, y, i);
+  const int Ly = ny * p + 1, rows = Ly * (nz * p + 1);
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+    const int J = row % Ly, K = row / Ly;
+    const bool face_row = !skip_interior || J % p == 0 || K % p == 0;
+    const int count = face_row ? nx * p + 1 : nx + 1;
+    if (t < count)
+      vec::gather_lattice_ijk<T>(yE, nx, ny, nz, p, constrained, accumulate, x, y,
+                                 face_row ? t : t * p, J, K);
+  }
 }
 
 template <typename T>
@@ -281,9 +292,14 @@ template <typename T>
 hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
                                  int accumulate, int skip_interior, const T* x, T* y,
                                  const int* skip, hipStream_t s) {
-  const int64_t n = ((int64_t)nx * p + 1) * ((int64_t)ny * p + 1) * ((int64_t)nz * p + 1);
-  hipLaunchKernelGGL((k_gather_lattice<T>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     s, yE, nx, ny, nz, p, constrained, accumulate, skip_interior, x, y, skip);
+  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
+  if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
+  if (Lx * Ly * Lz > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t rows = Ly * Lz;
+  const dim3 grid((unsigned)((Lx + kThreads - 1) / kThreads),
+                  (unsigned)(rows < 65535 ? rows : 65535));
+  hipLaunchKernelGGL((k_gather_lattice<T>), grid, dim3(kThreads), 0, s, yE, nx, ny, nz, p,
+                     constrained, accumulate, skip_interior, x, y, skip);
   return hipGetLastError();
 }
 template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int, int,

@@ -74,21 +74,16 @@ __device__ __forceinline__ void final_sums(const double* partials, int nb, int n
     for (int c = 0; c < ncols; ++c) out[c] = s[c][0];
 }
 
-// E^T at lattice node i: the sum of its element contributions in ascending
-// (element, local node) order; constrained essential rows take x[i] (or 0).
+// E^T at lattice node (I, J, K) of an (Lx, Ly, Lz) lattice: the sum of its
+// element contributions in ascending (element, local node) order; constrained
+// essential rows take x[i] (or 0).
 template <typename T>
-__device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, int nx, int ny,
-                                                    int nz, int p, int constrained,
-                                                    int accumulate, int skip_interior,
-                                                    const T* __restrict__ x, T* __restrict__ y,
-                                                    int64_t i) {
-  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
-  if (i >= Lx * Ly * Lz) return;
-  const int I = (int)(i % Lx);
-  const int J = (int)((i / Lx) % Ly);
-  const int K = (int)(i / (Lx * Ly));
-  // element-interior nodes were stored directly by the element kernel
-  if (skip_interior && I % p != 0 && J % p != 0 && K % p != 0) return;
+__device__ __forceinline__ void gather_lattice_ijk(const T* __restrict__ yE, int nx, int ny,
+                                                   int nz, int p, int constrained, int accumulate,
+                                                   const T* __restrict__ x, T* __restrict__ y,
+                                                   int I, int J, int K) {
+  const int Lx = nx * p + 1, Ly = ny * p + 1, Lz = nz * p + 1;
+  const int64_t i = I + (int64_t)Lx * (J + (int64_t)Ly * K);
   T acc = 0;
   const bool ess = I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1;
   if (constrained && ess) {
@@ -109,6 +104,23 @@ __device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, in
         }
   }
   y[i] = accumulate ? y[i] + acc : acc;
+}
+
+// The same at linear lattice index i; element-interior nodes (stored directly
+// by the element kernel) are skipped when skip_interior is set.
+template <typename T>
+__device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, int nx, int ny,
+                                                    int nz, int p, int constrained,
+                                                    int accumulate, int skip_interior,
+                                                    const T* __restrict__ x, T* __restrict__ y,
+                                                    int64_t i) {
+  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
+  if (i >= Lx * Ly * Lz) return;
+  const int I = (int)(i % Lx);
+  const int J = (int)((i / Lx) % Ly);
+  const int K = (int)(i / (Lx * Ly));
+  if (skip_interior && I % p != 0 && J % p != 0 && K % p != 0) return;
+  gather_lattice_ijk<T>(yE, nx, ny, nz, p, constrained, accumulate, x, y, I, J, K);
 }
 
 }  // namespace vec
