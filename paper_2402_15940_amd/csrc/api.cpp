@@ -159,16 +159,18 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   if (op->scatter_mode == PAFEM_SCATTER_ATOMIC && (flags & PAFEM_APPLY_CONSTRAINED))
     PAFEM_TRY(ensure_ess(sp, true));
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
-    PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
+    PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
+    // element pass into the E-vector, then the ordered per-node sum
     ApplyArgs<T> a = make_args<T>(op, x, y, op->d_evec.as<T>(), flags, skip, qprec);
-    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, PAFEM_SCATTER_DETERMINISTIC, im, a, s));
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q,
+                                  im == PAFEM_INDEX_MAP ? kScatterEvector : kScatterXRows, im, a, s));
     if (im == PAFEM_INDEX_MAP) {
       PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(),
                                         sp->d_et_idx.as<int32_t>(), a.ess_mask, a.constrained,
                                         a.accumulate, x, y, sp->ndofs, skip, s));
     } else {
-      PAFEM_TRY_HIP(launch_gather_lattice<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
-                                             a.accumulate, 1, x, y, skip, s));
+      PAFEM_TRY_HIP(launch_gather_xrows<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
+                                           a.accumulate, x, y, skip, s));
     }
   } else {
     ApplyArgs<T> a = make_args<T>(op, x, y, nullptr, flags, skip, qprec);
@@ -194,7 +196,7 @@ int gather_full(Op* op, const double* yE, int constrained, double* y, hipStream_
                                            y, sp->ndofs, nullptr, s));
   } else {
     PAFEM_TRY_HIP(launch_gather_lattice<double>(yE, sp->mesh->nx, sp->mesh->ny, sp->mesh->nz,
-                                                sp->p, constrained, 0, 0, nullptr, y, nullptr, s));
+                                                sp->p, constrained, 0, nullptr, y, nullptr, s));
   }
   return PAFEM_OK;
 }
@@ -205,7 +207,7 @@ int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
   (void)constrained;
   Space* sp = op->space;
   const int n = sp->p + 1;
-  PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
+  PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
   PAFEM_TRY_HIP(launch_diag_elem(op->kind, sp->p, op->q, op->d_qd64.as<double>(),
                                  tabB<double>(op->d_tab64), tabG<double>(op->d_tab64, op->q, n),
                                  sp->ne, op->d_evec.as<double>(), s));
@@ -340,8 +342,8 @@ int pafem_space_create(pafem_mesh* mesh, int p, pafem_space** out) {
   const int64_t ne = (int64_t)mesh->nx * mesh->ny * mesh->nz;
   const int64_t ndofs =
       ((int64_t)mesh->nx * p + 1) * ((int64_t)mesh->ny * p + 1) * ((int64_t)mesh->nz * p + 1);
-  CHECK_ARG(ne * n * n * n < std::numeric_limits<int32_t>::max(),
-            "ne*(p+1)^3 must fit in int32");
+  CHECK_ARG(evec_words(ne, (int)n) < std::numeric_limits<int32_t>::max(),
+            "the E-vector (about ne*(p+1)^3 words) must fit in int32 indexing");
   CHECK_ARG(ndofs < std::numeric_limits<int32_t>::max(), "ndofs must fit in int32");
   auto* sp = new pafem_space();
   sp->mesh = mesh;
@@ -656,7 +658,7 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_q, double* b, void* stream)
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   Space* sp = op->space;
   const int n = sp->p + 1;
-  PAFEM_TRY(op->d_evec.ensure((size_t)sp->ne * n * n * n * sizeof(double)));
+  PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
   GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, n), tabWts(op->d_tab64, op->q, n));
   hipStream_t s = S(stream);
   PAFEM_TRY_HIP(launch_rhs_elem(g, sp->p, tabB<double>(op->d_tab64), f_q, op->d_evec.as<double>(), s));

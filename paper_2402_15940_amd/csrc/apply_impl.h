@@ -82,6 +82,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 template <int P, int IDX, typename T>
 struct Restrict {
   const int32_t* Ee;
+  int ex, ey, ez;  // lattice element coordinates
   int I0, J0, K0;
   int Lx, Ly, Lz;
   __device__ __forceinline__ void init(const ApplyArgs<T>& a, int64_t e) {
@@ -93,9 +94,12 @@ struct Restrict {
       Ee = a.E + e * (N * N * N);
     } else {
       const int64_t t = e / a.nx;
-      I0 = (int)(e - t * a.nx) * P;
-      J0 = (int)(t % a.ny) * P;
-      K0 = (int)(t / a.ny) * P;
+      ex = (int)(e - t * a.nx);
+      ey = (int)(t % a.ny);
+      ez = (int)(t / a.ny);
+      I0 = ex * P;
+      J0 = ey * P;
+      K0 = ez * P;
     }
   }
   __device__ __forceinline__ int32_t dof(int aa, int b, int c) const {
@@ -121,26 +125,30 @@ __device__ __forceinline__ void scatter_add(T* p, T v) {
   atomicAdd(p, v);
 }
 
-// Where one element result goes:
-//   atomic         global FP64/FP32 atomic add into y (memory-side on MI355X);
-//   deterministic  element-interior nodes (owned by this element alone) are
-//                  stored to y directly when E is the lattice numbering; every
-//                  other node goes to the E-vector for the ordered per-dof sum;
-//   E-vector       every node goes to the E-vector.
+// Where the element results of one y-line (a, :, c) go: the E-vector, as
+// the output of the element pass itself or for the ordered per-node sum of
+// the deterministic E^T (element-major with a stored map, x-interleaved with
+// the lattice numbering), or global atomic adds into y (memory-side on MI355X).
 template <int P, int SCATTER, int IDX, typename T>
-__device__ __forceinline__ void store_result(const ApplyArgs<T>& a, const Restrict<P, IDX, T>& E,
-                                             int64_t e, int aa, int b, int c, bool interior,
-                                             T acc) {
+__device__ __forceinline__ void store_line(const ApplyArgs<T>& a, const Restrict<P, IDX, T>& E,
+                                           int64_t e, int aa, int c, const T (&acc)[P + 1]) {
   constexpr int N = P + 1;
-  if (SCATTER == kScatterEvector ||
-      (SCATTER == PAFEM_SCATTER_DETERMINISTIC && (IDX == PAFEM_INDEX_MAP || !interior))) {
-    a.yE[e * (N * N * N) + (c * N + b) * N + aa] = acc;
-  } else if (SCATTER == PAFEM_SCATTER_DETERMINISTIC) {
-    const int32_t g = E.dof(aa, b, c);
-    a.y[g] = a.accumulate ? a.y[g] + acc : acc;
+  if constexpr (SCATTER == kScatterXRows) {
+    static_assert(IDX == PAFEM_INDEX_LATTICE, "x-interleaved rows need the lattice numbering");
+    T* out = a.yE + xrows_index(a.nx, a.ny, N, E.ex, E.ey, E.ez, aa, 0, c);
+    const int stride = a.nx * xrows_width(N);
+#pragma unroll
+    for (int b = 0; b < N; ++b) out[b * stride] = acc[b];
+  } else if constexpr (SCATTER != PAFEM_SCATTER_ATOMIC) {
+    T* out = a.yE + e * (N * N * N) + c * N * N + aa;
+#pragma unroll
+    for (int b = 0; b < N; ++b) out[b * N] = acc[b];
   } else {
-    const int32_t g = E.dof(aa, b, c);
-    if (!(a.constrained && E.ess(a, g, aa, b, c))) scatter_add(a.y + g, acc);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const int32_t g = E.dof(aa, b, c);
+      if (!(a.constrained && E.ess(a, g, aa, b, c))) scatter_add(a.y + g, acc[b]);
+    }
   }
 }
 
@@ -336,10 +344,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
     }
     Restrict<P, IDX, T> E;
     E.init(a, eA);
-    const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
-#pragma unroll
-    for (int b = 0; b < N; ++b)
-      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc[b]);
+    store_line<P, SCATTER, IDX>(a, E, eA, aA, cA, acc);
   }
 }
 
@@ -467,10 +472,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     }
     Restrict<P, IDX, T> E;
     E.init(a, eA);
-    const bool interior = aA > 0 && aA < P && cA > 0 && cA < P;
-#pragma unroll
-    for (int b = 0; b < N; ++b)
-      store_result<P, SCATTER, IDX>(a, E, eA, aA, b, cA, interior && b > 0 && b < P, acc[b]);
+    store_line<P, SCATTER, IDX>(a, E, eA, aA, cA, acc);
   }
 }
 

@@ -210,9 +210,31 @@ struct ApplyArgs {
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
 };
 
-// Internal E^T mode: the full E-vector [ne][(p+1)^3] (element results before
-// assembly), used by pafem_op_apply_evector.
+// Internal output modes of the element pass: the full E-vector
+// [ne][(p+1)^3] (element results before assembly, pafem_op_apply_evector and
+// the stored-map deterministic E^T), and the same values with element rows
+// interleaved along x, [ez][ey][c][b][ex][a] (lattice numbering only), so that
+// the ordered per-node sum reads consecutive words for consecutive nodes.
 constexpr int kScatterEvector = 2;
+constexpr int kScatterXRows = 3;
+
+// Words per element run of the x-interleaved layout (runs may be padded so
+// that they fill whole memory sectors).
+#ifndef PAFEM_XROWS_PAD7
+#define PAFEM_XROWS_PAD7 7
+#endif
+__host__ __device__ constexpr int xrows_width(int n) { return n == 7 ? PAFEM_XROWS_PAD7 : n; }
+
+// Words of an E-vector buffer for either layout: ne (p+1)^2 max(p+1, width).
+inline int64_t evec_words(int64_t ne, int n) { return ne * n * n * xrows_width(n); }
+
+// Offset of local node (a, b, c) of element (ex, ey, ez) in the x-interleaved
+// layout (< evec_words < 2^31).
+__host__ __device__ __forceinline__ int xrows_index(int nx, int ny, int n, int ex, int ey, int ez,
+                                                    int a, int b, int c) {
+  const int w = xrows_width(n);
+  return (((ez * ny + ey) * n + c) * n + b) * (nx * w) + ex * w + a;
+}
 
 // y (atomic) or yE (deterministic) from one fused sum-factorized element pass.
 template <typename T>
@@ -234,11 +256,14 @@ hipError_t launch_gather_et(const T* yE, const int32_t* off, const int32_t* idx,
                             T* y, int64_t ndofs, const int* skip, hipStream_t s);
 // The same sum with the E-vector positions of each dof computed from the
 // lattice (same ascending (e, l) order, so bitwise equal to the CSR form).
-// skip_interior: element-interior nodes were already stored by the element kernel.
 template <typename T>
 hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
-                                 int accumulate, int skip_interior, const T* x, T* y,
-                                 const int* skip, hipStream_t s);
+                                 int accumulate, const T* x, T* y, const int* skip,
+                                 hipStream_t s);
+// The same sum from the x-interleaved layout.
+template <typename T>
+hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int constrained,
+                               int accumulate, const T* x, T* y, const int* skip, hipStream_t s);
 
 // Essential-dof fix-up: y[ess[i]] (+)= x ? x[ess[i]] : value.
 template <typename T>

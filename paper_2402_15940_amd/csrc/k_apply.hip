@@ -1,6 +1,6 @@
 // Per-operator launches of the fused partial-assembly element kernels
-// (bodies in apply_impl.h) and their dispatch over p, precision, E^T mode and
-// restriction source.
+// (bodies in apply_impl.h) and their dispatch over p, precision, output
+// (E-vector or atomic E^T) and restriction source.
 #include "apply_impl.h"
 
 namespace pafem {
@@ -50,13 +50,11 @@ hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s) {
 
 template <int P, typename T, int KIND>
 hipError_t apply_kind(int scatter, int idx, const ApplyArgs<T>& a, hipStream_t s) {
-  constexpr int DET = PAFEM_SCATTER_DETERMINISTIC, ATO = PAFEM_SCATTER_ATOMIC;
-  constexpr int EVC = kScatterEvector;
+  constexpr int ATO = PAFEM_SCATTER_ATOMIC, EVC = kScatterEvector, XR = kScatterXRows;
   constexpr int MAP = PAFEM_INDEX_MAP, LAT = PAFEM_INDEX_LATTICE;
+  if (scatter == XR) return launch_one<P, T, KIND, XR, LAT>(a, s);
   if (scatter == EVC)
     return idx == MAP ? launch_one<P, T, KIND, EVC, MAP>(a, s) : launch_one<P, T, KIND, EVC, LAT>(a, s);
-  if (scatter == DET)
-    return idx == MAP ? launch_one<P, T, KIND, DET, MAP>(a, s) : launch_one<P, T, KIND, DET, LAT>(a, s);
   return idx == MAP ? launch_one<P, T, KIND, ATO, MAP>(a, s) : launch_one<P, T, KIND, ATO, LAT>(a, s);
 }
 
@@ -73,6 +71,10 @@ template <typename T>
 hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode,
                         const ApplyArgs<T>& a, hipStream_t s) {
   if (q != p + 2) return hipErrorInvalidValue;
+  if (scatter_mode != PAFEM_SCATTER_ATOMIC && scatter_mode != kScatterEvector &&
+      scatter_mode != kScatterXRows)
+    return hipErrorInvalidValue;
+  if (scatter_mode == kScatterXRows && index_mode != PAFEM_INDEX_LATTICE) return hipErrorInvalidValue;
   // the stored maps must be on the device before a kernel may read them
   if (index_mode == PAFEM_INDEX_MAP && (a.E == nullptr || a.ess_mask == nullptr))
     return hipErrorInvalidValue;
@@ -80,7 +82,7 @@ hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode
       a.G == nullptr)
     return hipErrorInvalidValue;
   if (scatter_mode != PAFEM_SCATTER_ATOMIC && a.yE == nullptr) return hipErrorInvalidValue;
-  if (scatter_mode != kScatterEvector && a.y == nullptr) return hipErrorInvalidValue;
+  if (scatter_mode == PAFEM_SCATTER_ATOMIC && a.y == nullptr) return hipErrorInvalidValue;
   switch (p) {
     case 1: return apply_p<1, T>(kind, scatter_mode, index_mode, a, s);
     case 2: return apply_p<2, T>(kind, scatter_mode, index_mode, a, s);

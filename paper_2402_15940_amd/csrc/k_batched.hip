@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBatchThreads, (sizeof(T) == 4 ? 2 : 1)) void k_b_a
   __shared__ T smem[serve_lds_words<T>()];
   const int n = hdr->n;
   const int64_t total = hdr->total_work;
-  constexpr int DET = PAFEM_SCATTER_DETERMINISTIC, LAT = PAFEM_INDEX_LATTICE;
+  constexpr int DET = kScatterXRows, LAT = PAFEM_INDEX_LATTICE;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const BatchEntry<T>& E = ents[find_work(ents, n, w)];
     if (E.st->done) continue;  // the same for the whole workgroup
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(kBatchThreads, (sizeof(T) == 4 ? 2 : 1)) void k_b_a
   }
 }
 
-// E^T of the surface nodes (interior ones were stored by the element pass),
-// then the chunk's partial of dir . A dir.
+// E^T of the chunk's nodes from the x-interleaved E-vector, then the chunk's
+// partial of dir . A dir.
 template <typename T>
 __global__ __launch_bounds__(kBatchThreads) void k_b_gather_dot(
     const BatchEntry<T>* __restrict__ ents, const BatchHeader* __restrict__ hdr) {
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_b_gather_dot(
     for (int j = threadIdx.x; j < kBatchChunk; j += kBatchThreads) {
       const int64_t i = i0 + j;
       if (i < E.ndofs)
-        vec::gather_lattice_node<T>(E.a.yE, E.a.nx, E.a.ny, E.a.nz, E.p, 1, 0, 1, E.dir, E.Ad, i);
+        vec::gather_lattice_node<T, true>(E.a.yE, E.a.nx, E.a.ny, E.a.nz, E.p, 1, 0, E.dir, E.Ad, i);
     }
     __syncthreads();  // the chunk's A dir is complete (the block wrote it)
     double v[1] = {0.0}, out[1];

@@ -41,27 +41,97 @@ __global__ __launch_bounds__(kThreads) void k_gather_et(const T* __restrict__ yE
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
-// One workgroup per (slice of a) lattice row (J, K): a row that lies in an
-// element face plane (J or K a multiple of p) holds only surface nodes, every
-// other row only its x-face nodes I = f p once element-interior nodes are
-// skipped.  Index arithmetic stays 32-bit (lattice extents < 2^31).
-template <typename T>
+// E^T of a full E-vector (element-major, or x-interleaved when XROWS) on the
+// lattice numbering: one workgroup per (slice of a) lattice row (J, K), 32-bit
+// index arithmetic (extents < 2^31).
+template <typename T, bool XROWS>
 __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict__ yE, int nx,
                                                              int ny, int nz, int p,
                                                              int constrained, int accumulate,
-                                                             int skip_interior,
                                                              const T* __restrict__ x,
                                                              T* __restrict__ y, const int* skip) {
   if (skip != nullptr && *skip) return;
-  const int Ly = ny * p + 1, rows = Ly * (nz * p + 1);
-  const int t = blockIdx.x * kThreads + threadIdx.x;
-  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
-    const int J = row % Ly, K = row / Ly;
-    const bool face_row = !skip_interior || J % p == 0 || K % p == 0;
-    const int count = face_row ? nx * p + 1 : nx + 1;
-    if (t < count)
-      vec::gather_lattice_ijk<T>(yE, nx, ny, nz, p, constrained, accumulate, x, y,
-                                 face_row ? t : t * p, J, K);
+  const int Lx = nx * p + 1, Ly = ny * p + 1, rows = Ly * (nz * p + 1);
+  const int I = blockIdx.x * kThreads + threadIdx.x;
+  if (I >= Lx) return;
+  for (int row = blockIdx.y; row < rows; row += gridDim.y)
+    vec::gather_lattice_ijk<T, XROWS>(yE, nx, ny, nz, p, constrained, accumulate, x, y, I,
+                                      row % Ly, row / Ly);
+}
+
+// E^T from the x-interleaved E-vector: one workgroup per group of kXRowsPer
+// consecutive lattice rows (J, K), one thread per node I of those rows.  The
+// rows' (y, z) element candidates and the start of each candidate's run of
+// words are workgroup-uniform; node I = ex p + a reads word ex (p+1) + a of
+// every run (neighbouring threads: neighbouring words) and, on an x face
+// (a = 0, ex > 0), also the word before it (element ex-1, local p).  All loads
+// of the group are issued before the first sum, for memory-level parallelism.
+// Each node's sum runs in ascending (element, local node) order: for every
+// (z, y) candidate in ascending order, element ex-1 before element ex.
+constexpr int kXRowsPer = 4;
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__ yX, int nx,
+                                                           int ny, int nz, int constrained,
+                                                           int accumulate, const T* __restrict__ x,
+                                                           T* __restrict__ y, const int* skip) {
+  constexpr int N = P + 1, R = kXRowsPer;
+  if (skip != nullptr && *skip) return;
+  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1, rows = Ly * Lz;
+  const int I = blockIdx.x * kThreads + threadIdx.x;
+  if (I >= Lx) return;
+  int ex = I / P, a = I - ex * P;
+  if (ex == nx) {  // the row's last node
+    ex = nx - 1;
+    a = P;
+  }
+  const bool xface = a == 0 && ex > 0;
+  // word of node I in a run; left: offset of element ex-1's local p from it on
+  // x faces (0 elsewhere, so that the address stays in bounds)
+  constexpr int W = xrows_width(N);
+  const int col = ex * W + a, left = xface ? P - W : 0;
+  for (int row0 = blockIdx.y * R; row0 < rows; row0 += gridDim.y * R) {
+    T v[R][4], w[R][4];
+    int cy[R], cz[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = row0 + q < rows ? row0 + q : rows - 1;
+      const int J = row % Ly, K = row / Ly;
+      int ey[2], ly[2], ez[2], lz[2];
+      cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
+      cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
+#pragma unroll
+      for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 2; ++ky) {
+          const int k = 2 * kz + ky;
+          const bool on = kz < cz[q] && ky < cy[q];
+          const T* r = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
+          v[q][k] = on ? r[0] : T(0);
+          w[q][k] = (on && xface) ? r[left] : T(0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = row0 + q;
+      if (row >= rows) break;
+      const int J = row % Ly, K = row / Ly;
+      const int64_t i = I + (int64_t)Lx * row;
+      T acc = 0;
+      if (constrained && (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1)) {
+        acc = x ? x[i] : T(0);
+      } else {
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky)
+            if (kz < cz[q] && ky < cy[q]) {
+              if (xface) acc += w[q][2 * kz + ky];
+              acc += v[q][2 * kz + ky];
+            }
+      }
+      y[i] = accumulate ? y[i] + acc : acc;
+    }
   }
 }
 
@@ -288,23 +358,63 @@ template hipError_t launch_gather_et<float>(const float*, const int32_t*, const 
                                             const uint8_t*, int, int, const float*, float*,
                                             int64_t, const int*, hipStream_t);
 
-template <typename T>
-hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
-                                 int accumulate, int skip_interior, const T* x, T* y,
-                                 const int* skip, hipStream_t s) {
+template <typename T, bool XROWS>
+hipError_t gather_rows(const T* yE, int nx, int ny, int nz, int p, int constrained, int accumulate,
+                       const T* x, T* y, const int* skip, hipStream_t s) {
   const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
   if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
   if (Lx * Ly * Lz > 0x7fffffff) return hipErrorInvalidValue;
   const int64_t rows = Ly * Lz;
   const dim3 grid((unsigned)((Lx + kThreads - 1) / kThreads),
                   (unsigned)(rows < 65535 ? rows : 65535));
-  hipLaunchKernelGGL((k_gather_lattice<T>), grid, dim3(kThreads), 0, s, yE, nx, ny, nz, p,
-                     constrained, accumulate, skip_interior, x, y, skip);
+  hipLaunchKernelGGL((k_gather_lattice<T, XROWS>), grid, dim3(kThreads), 0, s, yE, nx, ny, nz, p,
+                     constrained, accumulate, x, y, skip);
   return hipGetLastError();
 }
-template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int, int,
+
+template <typename T>
+hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int constrained,
+                                 int accumulate, const T* x, T* y, const int* skip,
+                                 hipStream_t s) {
+  return gather_rows<T, false>(yE, nx, ny, nz, p, constrained, accumulate, x, y, skip, s);
+}
+template <typename T, int P>
+hipError_t gather_xrows_p(const T* yX, int nx, int ny, int nz, int constrained, int accumulate,
+                          const T* x, T* y, const int* skip, hipStream_t s) {
+  const int64_t Lx = (int64_t)nx * P + 1, rows = ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
+  const int64_t groups = (rows + kXRowsPer - 1) / kXRowsPer;
+  const dim3 grid((unsigned)((Lx + kThreads - 1) / kThreads),
+                  (unsigned)(groups < 65535 ? groups : 65535));
+  hipLaunchKernelGGL((k_gather_xrows<T, P>), grid, dim3(kThreads), 0, s, yX, nx, ny, nz,
+                     constrained, accumulate, x, y, skip);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int constrained,
+                               int accumulate, const T* x, T* y, const int* skip, hipStream_t s) {
+  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
+  if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
+  if (Lx * Ly * Lz > 0x7fffffff) return hipErrorInvalidValue;
+  switch (p) {
+    case 1: return gather_xrows_p<T, 1>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 2: return gather_xrows_p<T, 2>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 3: return gather_xrows_p<T, 3>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 4: return gather_xrows_p<T, 4>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 5: return gather_xrows_p<T, 5>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 6: return gather_xrows_p<T, 6>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 7: return gather_xrows_p<T, 7>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 8: return gather_xrows_p<T, 8>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_gather_xrows<double>(const double*, int, int, int, int, int, int,
+                                                const double*, double*, const int*, hipStream_t);
+template hipError_t launch_gather_xrows<float>(const float*, int, int, int, int, int, int,
+                                               const float*, float*, const int*, hipStream_t);
+template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int,
                                                   const double*, double*, const int*, hipStream_t);
-template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int, int,
+template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int,
                                                  const float*, float*, const int*, hipStream_t);
 
 template <typename T>

@@ -125,7 +125,7 @@ int64_t footprint_of(const pafem_request& r) {
   const bool ir = r.mode == PAFEM_SOLVE_IR_FP32;
   int64_t b = ne * q * q * q * 6 * 8;              // FP64 quadrature data
   if (ir) b += ne * q * q * q * 6 * 4;             // FP32 copy
-  b += ne * n * n * n * 8;                         // E-vector workspace
+  b += evec_words(ne, (int)n) * 8;                 // E-vector workspace
   b += nd * (5 * 8 + 8 + 4);                       // FP64 vectors, dinv (64 + 32)
   if (ir) b += nd * 4 * 4;                         // FP32 vectors
   b += (int64_t)(r.nx + 1) * (r.ny + 1) * (r.nz + 1) * 24;  // vertices
@@ -142,7 +142,7 @@ int request_valid(const pafem_request& r) {
   if (r.mode == PAFEM_SOLVE_IR_FP32 && (!(r.inner_rtol > 0.0) || r.max_outer < 1)) return 0;
   const int64_t ne = (int64_t)r.nx * r.ny * r.nz, n = r.p + 1;
   const int64_t nd = ((int64_t)r.nx * r.p + 1) * ((int64_t)r.ny * r.p + 1) * ((int64_t)r.nz * r.p + 1);
-  if (ne * n * n * n >= INT32_MAX || nd >= INT32_MAX) return 0;
+  if (evec_words(ne, (int)n) >= INT32_MAX || nd >= INT32_MAX) return 0;
   return 1;
 }
 

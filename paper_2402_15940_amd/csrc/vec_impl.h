@@ -50,8 +50,8 @@ __device__ __forceinline__ int lattice_cands(int I, int n, int p, int (&e)[2], i
   }
   int ee = I / p;
   if (ee > n - 1) ee = n - 1;
-  e[0] = ee;
-  l[0] = I - ee * p;
+  e[0] = e[1] = ee;  // the second entry repeats the first (always a valid position)
+  l[0] = l[1] = I - ee * p;
   return 1;
 }
 
@@ -74,10 +74,12 @@ __device__ __forceinline__ void final_sums(const double* partials, int nb, int n
     for (int c = 0; c < ncols; ++c) out[c] = s[c][0];
 }
 
-// E^T at lattice node (I, J, K) of an (Lx, Ly, Lz) lattice: the sum of its
-// element contributions in ascending (element, local node) order; constrained
-// essential rows take x[i] (or 0).
-template <typename T>
+// E^T at lattice node (I, J, K): the sum of its element contributions in the
+// E-vector (element-major, or x-interleaved when XROWS) in ascending
+// (element, local node) order (the order of the stored map's CSR sum, so the
+// forms agree bitwise); constrained essential rows take x[i] (or 0).  The up
+// to eight contributions are loaded together.
+template <typename T, bool XROWS = false>
 __device__ __forceinline__ void gather_lattice_ijk(const T* __restrict__ yE, int nx, int ny,
                                                    int nz, int p, int constrained, int accumulate,
                                                    const T* __restrict__ x, T* __restrict__ y,
@@ -89,38 +91,47 @@ __device__ __forceinline__ void gather_lattice_ijk(const T* __restrict__ yE, int
   if (constrained && ess) {
     acc = x ? x[i] : T(0);
   } else {
-    const int n = p + 1;
-    const int64_t nloc = (int64_t)n * n * n;
+    const int n = p + 1, nloc = n * n * n;  // ne (p+1)^3 < 2^31
     int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
     const int cx = lattice_cands(I, nx, p, ex, lx);
     const int cy = lattice_cands(J, ny, p, ey, ly);
     const int cz = lattice_cands(K, nz, p, ez, lz);
+    T v[8];
     // ascending element number: z outermost, x innermost
-    for (int kz = 0; kz < cz; ++kz)
-      for (int ky = 0; ky < cy; ++ky)
-        for (int kx = 0; kx < cx; ++kx) {
-          const int64_t e = ex[kx] + (int64_t)nx * (ey[ky] + (int64_t)ny * ez[kz]);
-          acc += yE[e * nloc + lx[kx] + n * (ly[ky] + n * lz[kz])];
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+          const int k = 4 * kz + 2 * ky + kx;
+          const bool on = kz < cz && ky < cy && kx < cx;
+          const int off = XROWS ? xrows_index(nx, ny, n, ex[kx], ey[ky], ez[kz], lx[kx], ly[ky], lz[kz])
+                                : (ex[kx] + nx * (ey[ky] + ny * ez[kz])) * nloc + lx[kx] +
+                                      n * (ly[ky] + n * lz[kz]);
+          v[k] = on ? yE[off] : T(0);
         }
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx)
+          if (kz < cz && ky < cy && kx < cx) acc += v[4 * kz + 2 * ky + kx];
   }
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
-// The same at linear lattice index i; element-interior nodes (stored directly
-// by the element kernel) are skipped when skip_interior is set.
-template <typename T>
+// The same at linear lattice index i (below the node count).
+template <typename T, bool XROWS = false>
 __device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, int nx, int ny,
                                                     int nz, int p, int constrained,
-                                                    int accumulate, int skip_interior,
-                                                    const T* __restrict__ x, T* __restrict__ y,
-                                                    int64_t i) {
-  const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
-  if (i >= Lx * Ly * Lz) return;
-  const int I = (int)(i % Lx);
-  const int J = (int)((i / Lx) % Ly);
-  const int K = (int)(i / (Lx * Ly));
-  if (skip_interior && I % p != 0 && J % p != 0 && K % p != 0) return;
-  gather_lattice_ijk<T>(yE, nx, ny, nz, p, constrained, accumulate, x, y, I, J, K);
+                                                    int accumulate, const T* __restrict__ x,
+                                                    T* __restrict__ y, int64_t i) {
+  const int Lx = nx * p + 1, Ly = ny * p + 1;
+  const int r = (int)(i / Lx);
+  gather_lattice_ijk<T, XROWS>(yE, nx, ny, nz, p, constrained, accumulate, x, y,
+                               (int)(i - (int64_t)r * Lx), r % Ly, r / Ly);
 }
 
 }  // namespace vec
