@@ -173,8 +173,26 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   const bool actC = sC < NE && eC < a.ne;
   const int qxC = rC % Q, qyC = rC / Q;
 
-  // Quadrature data of this thread's z-line, issued first: the dominant HBM
-  // stream, consumed only in stage C.
+  // stage-A role: y-line (a, c); lanes run along x so gather and scatter coalesce
+  const int sA = tid / (N * N), rA = tid - sA * (N * N);
+  const int64_t eA = e0 + sA;
+  const bool actA = sA < NE && eA < a.ne;
+  const int aA = rA % N, cA = rA / N;
+
+  // x gather of this thread's y-line, issued first and all at once: stage A
+  // waits for it alone (vector loads complete in order); the essential-dof
+  // mask is applied only after the quadrature-data loads are on their way
+  T u[N];
+  Restrict<P, IDX, T> EA;
+  if (actA) {
+    EA.init(a, eA);
+#pragma unroll
+    for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // Quadrature data of this thread's z-line: the dominant HBM stream, consumed
+  // only in stage C, so it streams in while stages A and B run.
   T dq[6][Q];
   if (actC) {
     const int64_t off = eC * (6 * QQQ) + qyC * Q + qxC;
@@ -193,24 +211,14 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
         for (int qz = 0; qz < Q; ++qz) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
     }
   }
+  __builtin_amdgcn_sched_barrier(0);
 
-  // stage-A role: y-line (a, c); lanes run along x so gather and scatter coalesce
-  const int sA = tid / (N * N), rA = tid - sA * (N * N);
-  const int64_t eA = e0 + sA;
-  const bool actA = sA < NE && eA < a.ne;
-  const int aA = rA % N, cA = rA / N;
-
-  // ---- stage A: gather + y contraction ----
+  // ---- stage A: y contraction ----
   if (actA) {
-    Restrict<P, IDX, T> E;
-    E.init(a, eA);
-    T u[N];
+    if (a.constrained) {
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int32_t g = E.dof(aA, b, cA);
-      T v = a.x[g];
-      if (a.constrained && E.ess(a, g, aA, b, cA)) v = T(0);
-      u[b] = v;
+      for (int b = 0; b < N; ++b)
+        if (EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) u[b] = T(0);
     }
     T* reg = smem + sA * L + (cA * Q) * R + aA;  // region (c, qy) at + qy*R
 #pragma unroll
@@ -363,6 +371,19 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   const int64_t eC = e0 + sC;
   const bool actC = sC < NE && eC < a.ne;
   const int qxC = rC % Q, qyC = rC / Q;
+  const int sA = tid / (N * N), rA = tid - sA * (N * N);
+  const int64_t eA = e0 + sA;
+  const bool actA = sA < NE && eA < a.ne;
+  const int aA = rA % N, cA = rA / N;
+  T u[N];  // x gather first, mask later (see diff_elements)
+  Restrict<P, IDX, T> EA;
+  if (actA) {
+    EA.init(a, eA);
+#pragma unroll
+    for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
   T dq[Q];
   if (actC) {
     const int64_t off = eC * QQQ + qyC * Q + qxC;
@@ -376,21 +397,13 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
       for (int qz = 0; qz < Q; ++qz) dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
     }
   }
+  __builtin_amdgcn_sched_barrier(0);
 
-  const int sA = tid / (N * N), rA = tid - sA * (N * N);
-  const int64_t eA = e0 + sA;
-  const bool actA = sA < NE && eA < a.ne;
-  const int aA = rA % N, cA = rA / N;
   if (actA) {
-    Restrict<P, IDX, T> E;
-    E.init(a, eA);
-    T u[N];
+    if (a.constrained) {
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int32_t g = E.dof(aA, b, cA);
-      T v = a.x[g];
-      if (a.constrained && E.ess(a, g, aA, b, cA)) v = T(0);
-      u[b] = v;
+      for (int b = 0; b < N; ++b)
+        if (EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) u[b] = T(0);
     }
     T* reg = smem + sA * L + (cA * Q) * R + aA;
 #pragma unroll
