@@ -158,7 +158,8 @@ __device__ __forceinline__ void store_line(const ApplyArgs<T>& a, const Restrict
 // ---------------------------------------------------------------------------
 // Elements e0 .. e0+NE-1 (those below a.ne) with the workgroup's threads;
 // smem holds NE * L words.  Every thread of the workgroup must call it.
-template <int P, int Q, typename T, int SCATTER, int IDX, int NE>
+// QD16: the quadrature data is stored in bfloat16 (a.qd16; FP32 arithmetic).
+template <int P, int Q, typename T, int SCATTER, int IDX, int NE, bool QD16 = false>
 __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0, T* smem,
                                               int tid) {
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
@@ -182,44 +183,46 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   // x gather of this thread's y-line, issued first and all at once: stage A
   // waits for it alone (vector loads complete in order); the essential-dof
   // mask is applied only after the quadrature-data loads are on their way
+  // All loads are unconditional (idle threads read element 0): a branch around
+  // them would make the compiler wait for every load before stage A.
   T u[N];
   Restrict<P, IDX, T> EA;
-  if (actA) {
-    EA.init(a, eA);
+  EA.init(a, actA ? eA : 0);
 #pragma unroll
-    for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
-  }
+  for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
   __builtin_amdgcn_sched_barrier(0);
 
   // Quadrature data of this thread's z-line: the dominant HBM stream, consumed
   // only in stage C, so it streams in while stages A and B run.
   T dq[6][Q];
-  if (actC) {
-    const int64_t off = eC * (6 * QQQ) + qyC * Q + qxC;
-    if (a.qd16 != nullptr) {  // BF16 storage, FP32 arithmetic (wave-uniform branch)
+  {
+    const int64_t off = (actC ? eC : 0) * (6 * QQQ) + qyC * Q + qxC;
+    if constexpr (QD16) {  // BF16 storage, FP32 arithmetic
       const uint16_t* qd = a.qd16 + off;
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
+      for (int qz = 0; qz < Q; ++qz)
 #pragma unroll
-        for (int qz = 0; qz < Q; ++qz)
+        for (int k = 0; k < 6; ++k)
           dq[k][qz] = (T)bf16_to_float(__builtin_nontemporal_load(qd + k * QQQ + qz * QQ));
     } else {
+      // issued in the order stage C consumes them (qz outer), so it can start
+      // on the first points while the rest are still arriving
       const T* qd = a.qd + off;
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
+      for (int qz = 0; qz < Q; ++qz) {
 #pragma unroll
-        for (int qz = 0; qz < Q; ++qz) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
+        for (int k = 0; k < 6; ++k) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
   __builtin_amdgcn_sched_barrier(0);
 
   // ---- stage A: y contraction ----
   if (actA) {
-    if (a.constrained) {
 #pragma unroll
-      for (int b = 0; b < N; ++b)
-        if (EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) u[b] = T(0);
-    }
+    for (int b = 0; b < N; ++b)  // a select, not a branch: no early wait on the loads
+      u[b] = (a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) ? T(0) : u[b];
     T* reg = smem + sA * L + (cA * Q) * R + aA;  // region (c, qy) at + qy*R
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {
@@ -359,7 +362,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
 // ---------------------------------------------------------------------------
 // mass: y_e = B^T D B x_e with D = w rho detJ.
 // ---------------------------------------------------------------------------
-template <int P, int Q, typename T, int SCATTER, int IDX, int NE>
+template <int P, int Q, typename T, int SCATTER, int IDX, int NE, bool QD16 = false>
 __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0, T* smem,
                                               int tid) {
   using C = Cfg<P, Q, T, PAFEM_MASS>;
@@ -375,19 +378,17 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   const int64_t eA = e0 + sA;
   const bool actA = sA < NE && eA < a.ne;
   const int aA = rA % N, cA = rA / N;
-  T u[N];  // x gather first, mask later (see diff_elements)
+  T u[N];  // x gather first, unconditional, masked later (see diff_elements)
   Restrict<P, IDX, T> EA;
-  if (actA) {
-    EA.init(a, eA);
+  EA.init(a, actA ? eA : 0);
 #pragma unroll
-    for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
-  }
+  for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
   __builtin_amdgcn_sched_barrier(0);
 
   T dq[Q];
-  if (actC) {
-    const int64_t off = eC * QQQ + qyC * Q + qxC;
-    if (a.qd16 != nullptr) {
+  {
+    const int64_t off = (actC ? eC : 0) * QQQ + qyC * Q + qxC;
+    if constexpr (QD16) {
       const uint16_t* qd = a.qd16 + off;
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) dq[qz] = (T)bf16_to_float(__builtin_nontemporal_load(qd + qz * QQ));
@@ -400,11 +401,9 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   __builtin_amdgcn_sched_barrier(0);
 
   if (actA) {
-    if (a.constrained) {
 #pragma unroll
-      for (int b = 0; b < N; ++b)
-        if (EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) u[b] = T(0);
-    }
+    for (int b = 0; b < N; ++b)
+      u[b] = (a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) ? T(0) : u[b];
     T* reg = smem + sA * L + (cA * Q) * R + aA;
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {

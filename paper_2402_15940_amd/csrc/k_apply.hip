@@ -1,6 +1,8 @@
 // Per-operator launches of the fused partial-assembly element kernels
 // (bodies in apply_impl.h) and their dispatch over p, precision, output
 // (E-vector or atomic E^T) and restriction source.
+#include <type_traits>
+
 #include "apply_impl.h"
 
 namespace pafem {
@@ -10,7 +12,7 @@ namespace {
 using apply::Cfg;
 using apply::xcd_block;
 
-template <int P, int Q, typename T, int SCATTER, int IDX>
+template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
                              (Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES)) void k_apply_diff(
     ApplyArgs<T> a) {
@@ -19,10 +21,10 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
   if (a.skip != nullptr && *a.skip) return;
   const int64_t nb = (a.ne + C::NE - 1) / C::NE;
   const int64_t e0 = xcd_block(blockIdx.x, nb) * C::NE;
-  apply::diff_elements<P, Q, T, SCATTER, IDX, C::NE>(a, e0, smem, threadIdx.x);
+  apply::diff_elements<P, Q, T, SCATTER, IDX, C::NE, QD16>(a, e0, smem, threadIdx.x);
 }
 
-template <int P, int Q, typename T, int SCATTER, int IDX>
+template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_mass(
     ApplyArgs<T> a) {
   using C = Cfg<P, Q, T, PAFEM_MASS>;
@@ -30,7 +32,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
   if (a.skip != nullptr && *a.skip) return;
   const int64_t nb = (a.ne + C::NE - 1) / C::NE;
   const int64_t e0 = xcd_block(blockIdx.x, nb) * C::NE;
-  apply::mass_elements<P, Q, T, SCATTER, IDX, C::NE>(a, e0, smem, threadIdx.x);
+  apply::mass_elements<P, Q, T, SCATTER, IDX, C::NE, QD16>(a, e0, smem, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -41,10 +43,21 @@ hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s) {
   constexpr int Q = P + 2;
   using C = Cfg<P, Q, T, KIND>;
   const int64_t nb = (a.ne + C::NE - 1) / C::NE;
+  // bfloat16 quadrature data is a compile-time variant (FP32 arithmetic only),
+  // so the FP64 and FP32 kernels carry no branch between their load streams
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.qd16 != nullptr) {
+      if (KIND == PAFEM_DIFFUSION)
+        hipLaunchKernelGGL((k_apply_diff<P, Q, T, SCATTER, IDX, true>), dim3(nb), dim3(C::THREADS), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_apply_mass<P, Q, T, SCATTER, IDX, true>), dim3(nb), dim3(C::THREADS), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (KIND == PAFEM_DIFFUSION)
-    hipLaunchKernelGGL((k_apply_diff<P, Q, T, SCATTER, IDX>), dim3(nb), dim3(C::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k_apply_diff<P, Q, T, SCATTER, IDX, false>), dim3(nb), dim3(C::THREADS), 0, s, a);
   else
-    hipLaunchKernelGGL((k_apply_mass<P, Q, T, SCATTER, IDX>), dim3(nb), dim3(C::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k_apply_mass<P, Q, T, SCATTER, IDX, false>), dim3(nb), dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
