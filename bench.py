@@ -15,10 +15,11 @@ The same JSON line also reports
   * cpu_baseline: the CPU oracle (CSR SpMV of the fully assembled matrix) on a
     bounded sample of the same workload (p = 6, smaller mesh), in GDOF/s;
   * cg: GDOF/s per Jacobi-PCG iteration in FP64 and in the FP32 inner solve;
-  * solve: plain FP64 CG vs FP32-inner/FP64-refined CG to rel. residual 1e-10
-    on the headline problem (manufactured sine solution, variable coefficient
-    k = 1 + 0.5 sin 2 pi x), and p50/p99 latency of a small Poisson solve
-    (4^3 affine mesh, p = 2);
+  * solve: plain FP64 CG vs the mixed-precision forms (one FP32/BF16-operator
+    CG with FP64 residual replacement; FP64 defect correction around FP32/BF16
+    inner CG) to rel. residual 1e-10 on the headline problem (manufactured sine
+    solution, variable coefficient k = 1 + 0.5 sin 2 pi x), and p50/p99 latency
+    of a small Poisson solve (4^3 affine mesh, p = 2);
   * sweep: FP64 diffusion/mass and FP32 diffusion apply GDOF/s for p = 1..8 at
     about 8M dofs;
   * serving: a seeded Poisson-arrival stream of Poisson solves (N in 8..20,
@@ -342,16 +343,19 @@ def main():
         Kc.set_scatter_mode(mode)
         bc = Kc.rhs()
         solves = {}
-        for name, md in (("plain_fp64", pf.SOLVE_PLAIN_FP64), ("ir_fp32", pf.SOLVE_IR_FP32),
-                         ("ir_bf16", pf.SOLVE_IR_BF16)):
+        for name, md, inner in (("plain_fp64", pf.SOLVE_PLAIN_FP64, 1e-4),
+                                ("mixed_fp32", pf.SOLVE_MIXED_FP32, 0.1),
+                                ("mixed_bf16", pf.SOLVE_MIXED_BF16, 0.1),
+                                ("ir_fp32", pf.SOLVE_IR_FP32, 1e-4),
+                                ("ir_bf16", pf.SOLVE_IR_BF16, 1e-4)):
             xs = torch.zeros_like(bc)
-            _, st = Kc.solve(bc, xs, mode=md, rtol=1e-10, inner_rtol=1e-4, maxit=20000,
+            _, st = Kc.solve(bc, xs, mode=md, rtol=1e-10, inner_rtol=inner, maxit=20000,
                              check_every=25)
             solves[name] = {k: (float(f"{v_:.4g}") if isinstance(v_, float) else v_)
                             for k, v_ in st.items()}
             solves[name]["x"] = xs
         x64 = solves["plain_fp64"]["x"]
-        for name in ("ir_fp32", "ir_bf16"):
+        for name in ("mixed_fp32", "mixed_bf16", "ir_fp32", "ir_bf16"):
             solves[name]["rel_diff_vs_plain"] = float((solves[name]["x"] - x64).norm() / x64.norm())
             solves[name]["speedup_vs_plain"] = round(solves["plain_fp64"]["seconds"] /
                                                      solves[name]["seconds"], 3)

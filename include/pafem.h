@@ -80,6 +80,10 @@ extern "C" {
 #define PAFEM_SOLVE_PLAIN_FP64 0 /* Jacobi-PCG entirely in FP64 */
 #define PAFEM_SOLVE_IR_FP32 1    /* FP64 defect correction around an FP32 Jacobi-PCG */
 #define PAFEM_SOLVE_IR_BF16 2    /* the same with bfloat16 quadrature data in the inner operator */
+#define PAFEM_SOLVE_MIXED_FP32 3 /* one Jacobi-PCG with an FP32 operator and Krylov vectors, the
+                                    solution accumulated in FP64 and the residual replaced by the
+                                    FP64 residual b - A x whenever it has fallen by inner_rtol */
+#define PAFEM_SOLVE_MIXED_BF16 4 /* the same with bfloat16 quadrature data in the FP32 operator */
 
 /* ---- opaque handles -------------------------------------------------------- */
 typedef struct pafem_ctx pafem_ctx;
@@ -203,17 +207,19 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_qpts_dev, double* b_dev, vo
 
 /* ---- solve ------------------------------------------------------------------- */
 typedef struct {
-  int mode;          /* PAFEM_SOLVE_PLAIN_FP64, PAFEM_SOLVE_IR_FP32 or PAFEM_SOLVE_IR_BF16 */
-  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for plain CG) */
-  double inner_rtol; /* IR: relative tolerance of each FP32 inner solve (e.g. 1e-4) */
-  int maxit;         /* plain: max CG iterations; IR: max inner iterations per solve */
-  int max_outer;     /* IR: max refinement steps */
+  int mode;          /* PAFEM_SOLVE_* */
+  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for plain CG;
+                        MIXED: confirmed on the FP64 residual) */
+  double inner_rtol; /* IR: relative tolerance of each FP32 inner solve (e.g. 1e-4);
+                        MIXED: residual drop that triggers a replacement, in (0, 1) (e.g. 0.1) */
+  int maxit;         /* plain, MIXED: max CG iterations; IR: max inner iterations per solve */
+  int max_outer;     /* IR: max refinement steps (MIXED: unused) */
   int check_every;   /* host reads the residual every this many iterations (>= 1) */
 } pafem_solve_opts;
 
 typedef struct {
-  int iterations;       /* plain: CG iterations; IR: total inner iterations */
-  int outer_iterations; /* IR: refinement steps (0 for plain) */
+  int iterations;       /* plain, MIXED: CG iterations; IR: total inner iterations */
+  int outer_iterations; /* IR: refinement steps; MIXED: residual replacements (0 for plain) */
   double rel_res;       /* final relative residual the stopping test saw */
   double true_rel_res;  /* ||b - A x||_2 / ||b||_2 recomputed in FP64 after the solve */
   double seconds;       /* wall time of the solve on the host clock */
@@ -223,8 +229,8 @@ typedef struct {
  * Jacobi preconditioning; x_dev holds the initial guess on entry (its
  * essential entries must equal b's) and the solution on return.
  * Synchronous.  NOT_CONVERGED if the iteration limit is hit (x then holds the
- * last iterate and stats are filled).  IR_FP32 needs the FP32 quadrature copy,
- * IR_BF16 the bfloat16 one. */
+ * last iterate and stats are filled).  IR_FP32 and MIXED_FP32 need the FP32
+ * quadrature copy, IR_BF16 and MIXED_BF16 the bfloat16 one. */
 int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem_solve_opts* opts,
                    pafem_solve_stats* stats, void* stream);
 

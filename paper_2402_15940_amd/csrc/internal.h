@@ -136,9 +136,12 @@ struct CgState {
   double rr_stop;  // stop when rr <= rr_stop
   double bb;       // b . b
   int iter;
-  int done;
+  int done;        // 1: converged or out of iterations; 2: paused for a residual replacement
   int maxit;
   int pad;
+  double rr_ref;   // r . r at the last residual replacement
+  double delta2;   // pause when rr <= delta2 rr_ref (0: never)
+  double rz_prev;  // r . z before the iteration that paused
 };
 
 struct Op : RefCounted {
@@ -286,10 +289,15 @@ template <typename T>
 hipError_t launch_cg_init(const T* r, const T* dinv, T* p, int64_t n, double* partials, int nb,
                           hipStream_t s);
 hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
-                                int maxit, CgState* st, hipStream_t s);
+                                int maxit, CgState* st, hipStream_t s, double delta2 = 0.0);
+// Mixed-precision CG: replace the FP32 recursive residual by rs = (float) r64
+// (r64 = b - A x in FP64), leaving partials of (rs . dinv rs, r64 . r64), and
+// (st non-null) finish the paused iteration's scalars from them.
+hipError_t launch_replace_residual(const double* r64, const float* dinv, float* rs, int64_t n,
+                                   double* partials, int nb, CgState* st, hipStream_t s);
 hipError_t launch_cg_alpha(const double* partials, int nb, CgState* st, hipStream_t s);
-template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, const T* Ap, const T* dinv, int64_t n,
+template <typename TX, typename T>
+hipError_t launch_cg_update(TX* x, T* r, const T* p, const T* Ap, const T* dinv, int64_t n,
                             double* partials, int nb, const CgState* st, hipStream_t s);
 hipError_t launch_cg_beta(const double* partials, int nb, CgState* st, hipStream_t s);
 template <typename T>

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(const T* __restrict__ r,
 }
 
 __global__ void k_cg_init_final(const double* __restrict__ partials, int nb, double bb,
-                                double rtol, int maxit, CgState* st) {
+                                double rtol, int maxit, double delta2, CgState* st) {
   double r[4];
   final_sums(partials, nb, 2, r);
   if (threadIdx.x == 0) {
@@ -217,6 +217,9 @@ __global__ void k_cg_init_final(const double* __restrict__ partials, int nb, dou
     st->iter = 0;
     st->maxit = maxit;
     st->done = (r[1] <= st->rr_stop) || maxit <= 0;
+    st->rr_ref = r[1];
+    st->delta2 = delta2;
+    st->rz_prev = 0.0;
   }
 }
 
@@ -230,9 +233,11 @@ __global__ void k_cg_alpha(const double* __restrict__ partials, int nb, CgState*
   }
 }
 
-// x += alpha p; r -= alpha Ap; partials of (r . z, r . r) with z = dinv .* r
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
+// x += alpha p; r -= alpha Ap; partials of (r . z, r . r) with z = dinv .* r.
+// With a wider solution type TX (FP64 x, FP32 Krylov vectors) the solution is
+// accumulated in TX with the FP64 alpha.
+template <typename TX, typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(TX* __restrict__ x, T* __restrict__ r,
                                                         const T* __restrict__ p,
                                                         const T* __restrict__ Ap,
                                                         const T* __restrict__ dinv, int64_t n,
@@ -240,10 +245,14 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* __restrict__ x, T* __
                                                         const CgState* __restrict__ st) {
   if (st->done) return;
   const T alpha = (T)st->alpha;
+  const double alpha_x = st->alpha;
   double v[2] = {0.0, 0.0}, out[2];
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
-    x[i] += alpha * p[i];
+    if constexpr (sizeof(TX) == sizeof(T))
+      x[i] += alpha * p[i];
+    else
+      x[i] += alpha_x * (TX)p[i];
     const T ri = r[i] - alpha * Ap[i];
     r[i] = ri;
     const T zi = dinv[i] * ri;
@@ -262,11 +271,15 @@ __global__ void k_cg_beta(const double* __restrict__ partials, int nb, CgState* 
   double r[4];
   final_sums(partials, nb, 2, r);
   if (threadIdx.x == 0) {
+    st->rz_prev = st->rz;
     st->beta = r[0] / st->rz;
     st->rz = r[0];
     st->rr = r[1];
     st->iter += 1;
-    if (r[1] <= st->rr_stop || st->iter >= st->maxit) st->done = 1;
+    if (r[1] <= st->rr_stop || st->iter >= st->maxit)
+      st->done = 1;
+    else if (st->delta2 > 0.0 && r[1] <= st->delta2 * st->rr_ref)
+      st->done = 2;  // the recursive residual fell by delta: replace it by the true one
   }
 }
 
@@ -284,6 +297,43 @@ __global__ __launch_bounds__(kThreads) void k_cg_pupdate(T* __restrict__ p,
 }
 
 // ---- mixed precision ------------------------------------------------------------
+
+// Residual replacement of the mixed-precision CG: rs = (float) r64 with r64 =
+// b - A x computed in FP64; partials of (rs . z, r64 . r64), z = dinv .* rs.
+__global__ __launch_bounds__(kThreads) void k_replace_residual(const double* __restrict__ r64,
+                                                               const float* __restrict__ dinv,
+                                                               float* __restrict__ rs, int64_t n,
+                                                               double* __restrict__ partials) {
+  double v[2] = {0.0, 0.0}, out[2];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double ri = r64[i];
+    const float rsi = (float)ri;
+    rs[i] = rsi;
+    v[0] += (double)rsi * (double)(dinv[i] * rsi);
+    v[1] += ri * ri;
+  }
+  block_sum<2>(v, out);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = out[0];
+    partials[2 * blockIdx.x + 1] = out[1];
+  }
+}
+
+// After a replacement: beta from the new r . z and the r . z before the
+// paused iteration, the true FP64 residual norm as rr and as the new
+// reference; done when the true residual meets the tolerance (or maxit).
+__global__ void k_replace_final(const double* __restrict__ partials, int nb, CgState* st) {
+  double r[4];
+  final_sums(partials, nb, 2, r);
+  if (threadIdx.x == 0) {
+    st->beta = st->rz_prev != 0.0 ? r[0] / st->rz_prev : 0.0;
+    st->rz = r[0];
+    st->rr = r[1];
+    st->rr_ref = r[1];
+    st->done = (r[1] <= st->rr_stop || st->iter >= st->maxit) ? 1 : 0;
+  }
+}
 
 __global__ __launch_bounds__(kThreads) void k_residual(const double* __restrict__ b,
                                                        const double* __restrict__ Ax,
@@ -468,9 +518,18 @@ template hipError_t launch_cg_init<float>(const float*, const float*, float*, in
                                           int, hipStream_t);
 
 hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
-                                int maxit, CgState* st, hipStream_t s) {
+                                int maxit, CgState* st, hipStream_t s, double delta2) {
   hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kThreads), 0, s, partials, nb, bb, rtol,
-                     maxit, st);
+                     maxit, delta2, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_replace_residual(const double* r64, const float* dinv, float* rs, int64_t n,
+                                   double* partials, int nb, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_replace_residual, dim3(nb), dim3(kThreads), 0, s, r64, dinv, rs, n,
+                     partials);
+  if (st != nullptr)
+    hipLaunchKernelGGL(k_replace_final, dim3(1), dim3(kThreads), 0, s, partials, nb, st);
   return hipGetLastError();
 }
 
@@ -479,19 +538,22 @@ hipError_t launch_cg_alpha(const double* partials, int nb, CgState* st, hipStrea
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, const T* Ap, const T* dinv, int64_t n,
+template <typename TX, typename T>
+hipError_t launch_cg_update(TX* x, T* r, const T* p, const T* Ap, const T* dinv, int64_t n,
                             double* partials, int nb, const CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(nb), dim3(kThreads), 0, s, x, r, p, Ap, dinv, n,
+  hipLaunchKernelGGL((k_cg_update<TX, T>), dim3(nb), dim3(kThreads), 0, s, x, r, p, Ap, dinv, n,
                      partials, st);
   return hipGetLastError();
 }
-template hipError_t launch_cg_update<double>(double*, double*, const double*, const double*,
-                                             const double*, int64_t, double*, int,
-                                             const CgState*, hipStream_t);
-template hipError_t launch_cg_update<float>(float*, float*, const float*, const float*,
-                                            const float*, int64_t, double*, int, const CgState*,
-                                            hipStream_t);
+template hipError_t launch_cg_update<double, double>(double*, double*, const double*,
+                                                     const double*, const double*, int64_t,
+                                                     double*, int, const CgState*, hipStream_t);
+template hipError_t launch_cg_update<float, float>(float*, float*, const float*, const float*,
+                                                   const float*, int64_t, double*, int,
+                                                   const CgState*, hipStream_t);
+template hipError_t launch_cg_update<double, float>(double*, float*, const float*, const float*,
+                                                    const float*, int64_t, double*, int,
+                                                    const CgState*, hipStream_t);
 
 hipError_t launch_cg_beta(const double* partials, int nb, CgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kThreads), 0, s, partials, nb, st);

@@ -1,5 +1,6 @@
 // Jacobi-preconditioned conjugate gradient on the partially assembled
-// operator, and FP64 defect correction around an FP32 inner PCG.
+// operator: plain FP64, FP64 defect correction around an FP32 inner PCG, and
+// one mixed-precision PCG with FP64 residual replacement.
 //
 // All CG scalars live in a device-resident CgState; one iteration is six
 // kernels (apply, p.Ap partial dot, alpha, update + (r.z, r.r) partials,
@@ -70,13 +71,79 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
       PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
       PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
       PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
-      PAFEM_TRY_HIP(launch_cg_update<T>(x, r, p, Ap, dinv, n, part, nb, st, s));
+      PAFEM_TRY_HIP((launch_cg_update<T, T>(x, r, p, Ap, dinv, n, part, nb, st, s)));
       PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
       PAFEM_TRY_HIP(launch_cg_pupdate<T>(p, r, dinv, n, st, s));
     }
     PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     PAFEM_TRY_HIP(hipStreamSynchronize(s));
     if (hs.done) break;
+  }
+  res.iterations = hs.iter;
+  res.rr = hs.rr;
+  res.converged = hs.rr <= hs.rr_stop;
+  return PAFEM_OK;
+}
+
+// Mixed-precision Jacobi-PCG with residual replacement: the operator, the
+// residual, direction and preconditioned vectors are FP32 (rs, p, Ap), the
+// solution is accumulated in FP64 with the FP64 alpha, all dot products
+// accumulate in FP64, and whenever the recursive residual has fallen by delta
+// since the last replacement (or meets the tolerance) it is replaced by the
+// FP64 residual b - A x (FP64 operator), keeping the search direction.
+// r64 and Ax are FP64 work vectors.
+int run_mixed(Op* op, const double* b, double* x, double* r64, double* Ax, float* rs, float* p,
+              float* Ap, const float* dinv, double rtol, double delta, int maxit,
+              int check_every, int qprec, hipStream_t s, CgResult& res, int& replacements) {
+  Space* sp = op->space;
+  const int64_t n = sp->ndofs;
+  const int nb = reduce_blocks(n);
+  PAFEM_TRY(op->d_part.ensure((size_t)nb * 2 * sizeof(double) + 8 * sizeof(double)));
+  PAFEM_TRY(op->d_state.ensure(sizeof(CgState)));
+  double* part = op->d_part.as<double>();
+  double* bbdev = part + 2 * nb;
+  CgState* st = op->d_state.as<CgState>();
+
+  PAFEM_TRY_HIP(launch_dot_partial<double>(b, b, n, part, nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, bbdev, s));
+  double bb = 0.0;
+  PAFEM_TRY_HIP(hipMemcpyAsync(&bb, bbdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
+  res.bb = bb;
+
+  // r64 = b - A x, rs = (float) r64, p = dinv .* rs
+  PAFEM_TRY(apply_impl<double>(op, x, Ax, PAFEM_APPLY_CONSTRAINED, nullptr, s));
+  PAFEM_TRY_HIP(launch_residual(b, Ax, r64, n, s));
+  PAFEM_TRY_HIP(launch_replace_residual(r64, dinv, rs, n, part, nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, bb, rtol, maxit, st, s, delta * delta));
+  PAFEM_TRY_HIP(launch_fill<float>(p, n, 0.0f, nullptr, s));
+  PAFEM_TRY_HIP(launch_cg_pupdate<float>(p, rs, dinv, n, st, s));  // beta = 0 here: p = z
+
+  const int* done = &st->done;
+  CgState hs{};
+  replacements = 0;
+  for (;;) {
+    for (int k = 0; k < check_every; ++k) {
+      PAFEM_TRY(apply_impl<float>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
+      PAFEM_TRY_HIP(launch_dot_partial<float>(p, Ap, n, part, nb, done, s));
+      PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
+      PAFEM_TRY_HIP((launch_cg_update<double, float>(x, rs, p, Ap, dinv, n, part, nb, st, s)));
+      PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+      PAFEM_TRY_HIP(launch_cg_pupdate<float>(p, rs, dinv, n, st, s));
+    }
+    PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    PAFEM_TRY_HIP(hipStreamSynchronize(s));
+    if (hs.done == 0) continue;
+    // paused, converged on the recursive residual, or out of iterations:
+    // replace the residual by the FP64 one, which also decides convergence
+    PAFEM_TRY(apply_impl<double>(op, x, Ax, PAFEM_APPLY_CONSTRAINED, nullptr, s));
+    PAFEM_TRY_HIP(launch_residual(b, Ax, r64, n, s));
+    PAFEM_TRY_HIP(launch_replace_residual(r64, dinv, rs, n, part, nb, st, s));
+    ++replacements;
+    PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    PAFEM_TRY_HIP(hipStreamSynchronize(s));
+    if (hs.done) break;
+    PAFEM_TRY_HIP(launch_cg_pupdate<float>(p, rs, dinv, n, st, s));  // p = z + beta p
   }
   res.iterations = hs.iter;
   res.rr = hs.rr;
@@ -138,14 +205,18 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     set_error("need rtol > 0, maxit >= 1, check_every >= 1");
     return PAFEM_ERR_INVALID_ARG;
   }
-  if (o->mode != PAFEM_SOLVE_PLAIN_FP64 && o->mode != PAFEM_SOLVE_IR_FP32 &&
-      o->mode != PAFEM_SOLVE_IR_BF16) {
+  if (o->mode < PAFEM_SOLVE_PLAIN_FP64 || o->mode > PAFEM_SOLVE_MIXED_BF16) {
     set_error("unknown solve mode");
     return PAFEM_ERR_INVALID_ARG;
   }
+  const bool mixed = o->mode == PAFEM_SOLVE_MIXED_FP32 || o->mode == PAFEM_SOLVE_MIXED_BF16;
+  if (mixed && !(o->inner_rtol > 0.0 && o->inner_rtol < 1.0)) {
+    set_error("MIXED modes need inner_rtol (the replacement factor) in (0, 1)");
+    return PAFEM_ERR_INVALID_ARG;
+  }
   const bool ir = o->mode != PAFEM_SOLVE_PLAIN_FP64;
-  if (!op->have64 || (o->mode == PAFEM_SOLVE_IR_FP32 && !op->have32) ||
-      (o->mode == PAFEM_SOLVE_IR_BF16 && !op->have16)) {
+  const bool bf16 = o->mode == PAFEM_SOLVE_IR_BF16 || o->mode == PAFEM_SOLVE_MIXED_BF16;
+  if (!op->have64 || (ir && !bf16 && !op->have32) || (bf16 && !op->have16)) {
     set_error("operator not assembled in the precision the mode needs");
     return PAFEM_ERR_INVALID_ARG;
   }
@@ -169,7 +240,21 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
   double* Ap = p + n;
 
   int rc = PAFEM_OK;
-  if (o->mode == PAFEM_SOLVE_PLAIN_FP64) {
+  if (mixed) {
+    float* rs = reinterpret_cast<float*>(Ap + n);
+    float* p32 = rs + n;
+    float* Ap32 = p32 + n;
+    CgResult res;
+    int repl = 0;
+    PAFEM_TRY(run_mixed(op, b, x, r, p, rs, p32, Ap32, op->d_dinv32.as<float>(), o->rtol,
+                        o->inner_rtol, o->maxit, o->check_every, bf16 ? PAFEM_BF16 : PAFEM_FP32,
+                        s, res, repl));
+    stats->iterations = res.iterations;
+    stats->outer_iterations = repl;
+    stats->rel_res = res.bb > 0 ? std::sqrt(res.rr / res.bb) : std::sqrt(res.rr);
+    PAFEM_TRY(true_residual(op, b, x, Ap, r, res.bb, s, stats->true_rel_res));
+    if (!res.converged) rc = PAFEM_ERR_NOT_CONVERGED;
+  } else if (o->mode == PAFEM_SOLVE_PLAIN_FP64) {
     CgResult res;
     PAFEM_TRY(run_pcg<double>(op, b, x, false, r, p, Ap, op->d_dinv64.as<double>(), o->rtol,
                               o->maxit, o->check_every, s, res));

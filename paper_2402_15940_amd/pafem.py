@@ -31,6 +31,8 @@ APPLY_ACCUMULATE = 2
 SOLVE_PLAIN_FP64 = 0
 SOLVE_IR_FP32 = 1
 SOLVE_IR_BF16 = 2
+SOLVE_MIXED_FP32 = 3
+SOLVE_MIXED_BF16 = 4
 
 _ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "NOT_CONVERGED",
            -5: "UNSUPPORTED", -6: "NO_DEVICE"}

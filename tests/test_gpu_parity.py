@@ -300,13 +300,22 @@ def test_poisson_perturbed_plain_and_mixed(pf, ctx, p):
     op.assemble(pf.FP64 | pf.FP32)
     b = op.rhs()
     xr = ref["x"]
-    for mode in (pf.SOLVE_PLAIN_FP64, pf.SOLVE_IR_FP32):
-        x, st = op.solve(b, mode=mode, rtol=1e-10, inner_rtol=1e-3)
+    its = {}
+    for mode, inner in ((pf.SOLVE_PLAIN_FP64, 1e-3), (pf.SOLVE_IR_FP32, 1e-3),
+                        (pf.SOLVE_MIXED_FP32, 0.1)):
+        x, st = op.solve(b, mode=mode, rtol=1e-10, inner_rtol=inner)
         assert st["true_rel_res"] <= 1.5e-10, (mode, st)
         err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
         assert err <= 1e-8, (mode, err)
+        its[mode] = st["iterations"]
         if mode == pf.SOLVE_IR_FP32:
             assert st["outer_iterations"] >= 2
+        if mode == pf.SOLVE_MIXED_FP32:
+            # the FP64 residual is confirmed at the end and replaced on the way
+            assert st["true_rel_res"] <= 1e-10 and st["outer_iterations"] >= 3
+    # one Krylov space: about the plain iteration count (a restarted defect
+    # correction needs far more)
+    assert its[pf.SOLVE_MIXED_FP32] <= 1.3 * its[pf.SOLVE_PLAIN_FP64] + 5, its
 
 
 def test_solve_not_converged_reports(pf, ctx):
@@ -501,3 +510,32 @@ def test_bf16_refined_solve_reaches_fp64_accuracy(pf, ctx):
     xb, sb = op.solve(b, mode=pf.SOLVE_IR_BF16, rtol=1e-10, inner_rtol=1e-3)
     assert sb["true_rel_res"] <= 1e-10 and sb["outer_iterations"] >= 2
     assert ((xb - x64).norm() / x64.norm()).item() < 1e-8
+    xm, sm = op.solve(b, mode=pf.SOLVE_MIXED_BF16, rtol=1e-10, inner_rtol=0.1)
+    assert sm["true_rel_res"] <= 1e-10 and sm["outer_iterations"] >= 2
+    assert ((xm - x64).norm() / x64.norm()).item() < 1e-8
+
+
+def test_mixed_solve_limits_and_nonzero_guess(pf, ctx):
+    n, p = 3, 3
+    v = inputs.perturbed_vertices(n, n, n, seed=2)
+    op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, v), p), pf.DIFFUSION)
+    op.assemble(pf.FP64 | pf.FP32)
+    b = op.rhs()
+    x, st = op.solve(b, mode=pf.SOLVE_MIXED_FP32, rtol=1e-14, inner_rtol=0.1, maxit=3,
+                     raise_on_nonconvergence=False)
+    assert st["iterations"] == 3 and st["true_rel_res"] > 1e-14
+    with pytest.raises(pf.PafemError) as ei:
+        op.solve(b, mode=pf.SOLVE_MIXED_FP32, rtol=1e-14, inner_rtol=0.1, maxit=3)
+    assert ei.value.name == "NOT_CONVERGED"
+    for bad in (0.0, 1.5):
+        with pytest.raises(pf.PafemError) as ei:
+            op.solve(b, mode=pf.SOLVE_MIXED_FP32, inner_rtol=bad)
+        assert ei.value.name == "INVALID_ARG"
+    with pytest.raises(pf.PafemError) as ei:
+        op.solve(b, mode=7)
+    assert ei.value.name == "INVALID_ARG"
+    # restart from the last iterate: the first FP64 residual accounts for it
+    x2, st2 = op.solve(b, x.clone(), mode=pf.SOLVE_MIXED_FP32, rtol=1e-10, inner_rtol=0.1)
+    x64, _ = op.solve(b, mode=pf.SOLVE_PLAIN_FP64, rtol=1e-12)
+    assert st2["true_rel_res"] <= 1e-10
+    assert ((x2 - x64).norm() / x64.norm()).item() < 1e-8
