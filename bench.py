@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the p=7 64^3 (90M dofs) single solve")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rates", type=str, default="20,80,320",
                     help="arrival rates (requests/s) of the serving stream")
@@ -382,6 +384,57 @@ def main():
         log(f"small solve {extra['solve_small']}")
     del ops, K
     torch.cuda.synchronize()
+
+    # ---- large single solve: p = 7 on a 64^3 perturbed mesh (90,518,849 dofs) --------
+    if not args.no_large and not args.no_solve:
+        pL, NL = 7, 64
+        vL = inputs.perturbed_vertices(NL, NL, NL, seed=inputs.mesh_seed(pL, NL))
+        spL = pf.Space(pf.Mesh(ctx, NL, NL, NL, vL), pL)
+        KL = pf.Operator(spL, pf.DIFFUSION)
+        KL.assemble(pf.FP64 | pf.FP32)
+        KL.set_scatter_mode(mode)
+        ndL, neL, qL = spL.ndofs, spL.nelems, pL + 2
+        xL = torch.from_numpy(inputs.random_vector(ndL, inputs.vector_seed(pL, NL))).cuda()
+        yL = torch.empty_like(xL)
+        t_ap, _ = time_applies(torch, KL, xL, yL, 10, 2)
+        yEL = torch.empty(neL * (pL + 1) ** 3, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            KL.apply_evector(xL, yEL)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            KL.apply_evector(xL, yEL)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ev = e0.elapsed_time(e1) / 10
+        del yEL, xL, yL
+        bL = KL.rhs()
+        large = {"problem": "p=7, 64^3 perturbed hex mesh, k=1, 90,518,849 dofs, Jacobi-PCG to 1e-10",
+                 "ndofs": ndL, "qdata_gb_fp64": round(neL * qL ** 3 * 48 / 1e9, 3),
+                 "apply_ms": round(t_ap, 4), "apply_gdofs": round(ndL / t_ap / 1e6, 3),
+                 "element_pass_ms": round(t_ev, 4),
+                 "element_pass_gbs": round(apply_bytes(neL, pL + 1, qL, 6, ndL, 8) / t_ev / 1e6, 1)}
+        large["element_pass_hbm_frac"] = round(large["element_pass_gbs"] / HBM_PEAK_GBS, 4)
+        xs64 = None
+        for name, md, inner in (("plain_fp64", pf.SOLVE_PLAIN_FP64, 1e-4),
+                                ("mixed_fp32", pf.SOLVE_MIXED_FP32, 0.1)):
+            xs = torch.zeros_like(bL)
+            _, st = KL.solve(bL, xs, mode=md, rtol=1e-10, inner_rtol=inner, maxit=50000,
+                             check_every=50)
+            large[name] = {k: (float(f"{v_:.4g}") if isinstance(v_, float) else v_)
+                           for k, v_ in st.items()}
+            if xs64 is None:
+                xs64 = xs
+            else:
+                large[name]["rel_diff_vs_plain"] = float((xs - xs64).norm() / xs64.norm())
+                large[name]["speedup_vs_plain"] = round(large["plain_fp64"]["seconds"] /
+                                                        large[name]["seconds"], 3)
+            log(f"large solve {name}: {large[name]}")
+        extra["solve_large"] = large
+        log(f"large {large}")
+        del KL, bL, xs, xs64
+        torch.cuda.synchronize()
 
     # ---- sweep over p ---------------------------------------------------------------
     if not args.no_sweep:
