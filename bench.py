@@ -163,8 +163,8 @@ def serve_benchmark(pf, ctx, rate, n_req, n_range, p_range, budget, max_slots, i
         if dt > 0:
             time.sleep(dt)
         n = r["N"]
-        tickets.append(srv.submit(n, n, n, r["p"], v, mode=pf.SOLVE_IR_FP32, rtol=1e-10,
-                                  inner_rtol=1e-4, coef_kind=pf.COEF_CONST, coef_value=1.0))
+        tickets.append(srv.submit(n, n, n, r["p"], v, mode=pf.SOLVE_MIXED_FP32, rtol=1e-10,
+                                  inner_rtol=0.1, coef_kind=pf.COEF_CONST, coef_value=1.0))
     srv.drain()
     res = [srv.poll(t) for t in tickets]
     st = srv.stats()
@@ -179,6 +179,7 @@ def serve_benchmark(pf, ctx, rate, n_req, n_range, p_range, budget, max_slots, i
             "p50_ms": round(float(np.percentile(lat, 50)), 2) if len(lat) else None,
             "p99_ms": round(float(np.percentile(lat, 99)), 2) if len(lat) else None,
             "aggregate_gdofs": round(dof_it / (t_last - t_first) / 1e9, 3),
+            "solves_per_s": round(len(ok) / (t_last - t_first), 2),
             "wall_s": round(t_last - t_first, 3), "max_active": st["max_active"],
             "rounds": st["rounds"], "peak_gb": round(st["peak_bytes"] / 1e9, 3),
             "mean_ndofs": int(np.mean([r["ndofs"] for r in res]))}

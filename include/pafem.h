@@ -271,9 +271,9 @@ typedef struct {
   const double* verts_host; /* [(nx+1)(ny+1)(nz+1)][3], copied by pafem_server_submit */
   int coef_kind;            /* PAFEM_COEF_CONST or PAFEM_COEF_SINX */
   double coef_value;
-  int mode;                 /* PAFEM_SOLVE_PLAIN_FP64 or PAFEM_SOLVE_IR_FP32 */
+  int mode;                 /* PAFEM_SOLVE_PLAIN_FP64, PAFEM_SOLVE_IR_FP32 or PAFEM_SOLVE_MIXED_FP32 */
   double rtol;              /* relative residual target (FP64) */
-  double inner_rtol;        /* IR: inner FP32 relative tolerance */
+  double inner_rtol;        /* IR: inner FP32 relative tolerance; MIXED: replacement factor in (0, 1) */
   int maxit;                /* CG iteration limit (per inner solve for IR) */
   int max_outer;            /* IR: refinement step limit */
 } pafem_request;
@@ -284,7 +284,7 @@ typedef struct {
   int64_t ndofs;
   int64_t footprint_bytes;  /* device bytes reserved while admitted */
   int iterations;           /* CG iterations (inner total for IR) */
-  int outer_iterations;
+  int outer_iterations;     /* IR: refinement steps; MIXED: residual replacements */
   double rel_res;           /* final ||b - A x|| / ||b|| in FP64 */
   double t_arrive, t_admit, t_done; /* seconds on the server clock (-1 if not yet) */
 } pafem_result;

@@ -327,6 +327,7 @@ struct BatchEntry {
   const T* dinv;
   CgState* st;
   double* partials;         // [nchunks][2]
+  double* x64;              // non-null: the solution is accumulated here in FP64 (mixed CG)
 };
 
 struct BatchHeader {

@@ -123,12 +123,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_b_update(const BatchEntry<T>*
     const BatchEntry<T>& E = ents[find_chunk(ents, n, c)];
     if (E.st->done) continue;
     const T alpha = (T)E.st->alpha;
+    const double alpha_x = E.st->alpha;
     const int64_t k = c - E.chunk_begin;
     double v[2] = {0.0, 0.0}, out[2];
     for (int j = threadIdx.x; j < kBatchChunk; j += kBatchThreads) {
       const int64_t i = k * kBatchChunk + j;
       if (i < E.ndofs) {
-        E.x[i] += alpha * E.dir[i];
+        if (E.x64 != nullptr)  // mixed CG: FP64 solution, FP64 alpha (uniform per entry)
+          E.x64[i] += alpha_x * (double)E.dir[i];
+        else
+          E.x[i] += alpha * E.dir[i];
         const T ri = E.r[i] - alpha * E.Ad[i];
         E.r[i] = ri;
         const T zi = E.dinv[i] * ri;
@@ -155,11 +159,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_b_beta(const BatchEntry<T>* _
   double r[4];
   vec::final_sums(E.partials, E.nchunks, 2, r);
   if (threadIdx.x == 0) {
+    st->rz_prev = st->rz;
     st->beta = r[0] / st->rz;
     st->rz = r[0];
     st->rr = r[1];
     st->iter += 1;
-    if (r[1] <= st->rr_stop || st->iter >= st->maxit) st->done = 1;
+    if (r[1] <= st->rr_stop || st->iter >= st->maxit)
+      st->done = 1;
+    else if (st->delta2 > 0.0 && r[1] <= st->delta2 * st->rr_ref)
+      st->done = 2;  // mixed CG: pause for a residual replacement
   }
 }
 

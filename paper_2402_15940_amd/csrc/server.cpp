@@ -3,7 +3,9 @@
 // Host side: a request queue (thread-safe submit/poll), FIFO admission while a
 // slot is free and the request's device footprint fits the budget, and one
 // engine thread that owns all device work.  Device side: two batches (FP64
-// CG for plain requests, FP32 CG for the inner solves of refined requests);
+// CG for plain requests; FP32-operator CG for the inner solves of refined
+// requests and for mixed requests, whose solution is kept in FP64 and whose
+// residual is replaced by the FP64 one between rounds);
 // every round replays one captured HIP graph per non-empty batch.  The graph's
 // kernels read the batch membership from a device table, so admission and
 // retirement only rewrite that table between replays.
@@ -51,7 +53,8 @@ struct Req {
   DevBuf v32;   // d, r, dir, Ad (inner FP32 solve)
   DevBuf part;  // reduction partials + device scalars
   double bb = 0.0;
-  bool ir = false;
+  bool ir = false;     // FP64 defect correction around FP32 inner solves
+  bool mixed = false;  // one FP32 CG with FP64 solution and residual replacement
   double* b() const { return v64.as<double>(); }
   double* x() const { return v64.as<double>() + ndofs; }
   double* r() const { return v64.as<double>() + 2 * ndofs; }
@@ -122,7 +125,7 @@ int64_t footprint_of(const pafem_request& r) {
   const int64_t p = r.p, n = p + 1, q = p + 2;
   const int64_t ne = (int64_t)r.nx * r.ny * r.nz;
   const int64_t nd = ((int64_t)r.nx * p + 1) * ((int64_t)r.ny * p + 1) * ((int64_t)r.nz * p + 1);
-  const bool ir = r.mode == PAFEM_SOLVE_IR_FP32;
+  const bool ir = r.mode == PAFEM_SOLVE_IR_FP32 || r.mode == PAFEM_SOLVE_MIXED_FP32;
   int64_t b = ne * q * q * q * 6 * 8;              // FP64 quadrature data
   if (ir) b += ne * q * q * q * 6 * 4;             // FP32 copy
   b += evec_words(ne, (int)n) * 8;                 // E-vector workspace
@@ -136,7 +139,10 @@ int64_t footprint_of(const pafem_request& r) {
 int request_valid(const pafem_request& r) {
   if (footprint_of(r) < 0) return 0;
   if (r.verts_host == nullptr) return 0;
-  if (r.mode != PAFEM_SOLVE_PLAIN_FP64 && r.mode != PAFEM_SOLVE_IR_FP32) return 0;
+  if (r.mode != PAFEM_SOLVE_PLAIN_FP64 && r.mode != PAFEM_SOLVE_IR_FP32 &&
+      r.mode != PAFEM_SOLVE_MIXED_FP32)
+    return 0;
+  if (r.mode == PAFEM_SOLVE_MIXED_FP32 && !(r.inner_rtol > 0.0 && r.inner_rtol < 1.0)) return 0;
   if (r.coef_kind != PAFEM_COEF_CONST && r.coef_kind != PAFEM_COEF_SINX) return 0;
   if (!(r.rtol > 0.0) || r.maxit < 1) return 0;
   if (r.mode == PAFEM_SOLVE_IR_FP32 && (!(r.inner_rtol > 0.0) || r.max_outer < 1)) return 0;
@@ -186,6 +192,7 @@ BatchEntry<T> make_entry(Server& S, Req* r, int64_t work_begin, int64_t chunk_be
   e.chunk_end = chunk_begin + e.nchunks;
   e.st = S.d_states.as<CgState>() + r->slot;
   e.partials = r->partials();
+  e.x64 = r->mixed ? r->x() : nullptr;
   if (f32) {
     e.x = (T*)r->d32();
     e.r = (T*)r->r32();
@@ -296,17 +303,31 @@ int setup(Server& S, Req* r) {
     PAFEM_TRY(pafem_op_set_coefficient_sinx(r->op, q.coef_value));
   else
     PAFEM_TRY(pafem_op_set_coefficient_const(r->op, q.coef_value));
-  PAFEM_TRY(pafem_op_assemble(r->op, PAFEM_FP64 | (r->ir ? PAFEM_FP32 : 0), S.stream));
+  const bool f32 = r->ir || r->mixed;
+  PAFEM_TRY(pafem_op_assemble(r->op, PAFEM_FP64 | (f32 ? PAFEM_FP32 : 0), S.stream));
   const int64_t n = r->ndofs;
   PAFEM_TRY(r->v64.ensure(5 * n * sizeof(double)));
-  if (r->ir) PAFEM_TRY(r->v32.ensure(4 * n * sizeof(float)));
+  if (f32) PAFEM_TRY(r->v32.ensure(4 * n * sizeof(float)));
   PAFEM_TRY(r->part.ensure((r->nparts() + 8) * sizeof(double)));
   PAFEM_TRY(pafem_rhs_assemble(r->op, nullptr, r->b(), S.stream));
-  PAFEM_TRY(ensure_dinv(r->op, S.stream, r->ir));
+  PAFEM_TRY(ensure_dinv(r->op, S.stream, f32));
   PAFEM_TRY_HIP(launch_fill<double>(r->x(), n, 0.0, nullptr, S.stream));
   PAFEM_TRY_HIP(hipMemcpyAsync(r->r(), r->b(), n * sizeof(double), hipMemcpyDeviceToDevice,
                                S.stream));
   PAFEM_TRY(dot_to_host(S, r, r->b(), r->b(), r->rr_dev(), r->bb));
+  if (r->mixed) {
+    // x = 0: the FP64 residual is b; rs = (float) b, dir = dinv .* rs
+    const int nb = reduce_blocks(n);
+    CgState* st = S.d_states.as<CgState>() + r->slot;
+    const float* dinv32 = r->op->d_dinv32.as<float>();
+    PAFEM_TRY_HIP(launch_replace_residual(r->r(), dinv32, r->r32(), n, r->partials(), nb, nullptr,
+                                          S.stream));
+    PAFEM_TRY_HIP(launch_cg_init_final(r->partials(), nb, r->bb, q.rtol, q.maxit, st, S.stream,
+                                       q.inner_rtol * q.inner_rtol));
+    PAFEM_TRY_HIP(launch_fill<float>(r->dir32(), n, 0.0f, nullptr, S.stream));
+    PAFEM_TRY_HIP(launch_cg_pupdate<float>(r->dir32(), r->r32(), dinv32, n, st, S.stream));
+    return PAFEM_OK;
+  }
   if (r->ir) return start_inner(S, r);  // rr_dev holds ||r||^2 = ||b||^2
   return cg_start<double>(S, r, r->r(), r->dir(), r->op->d_dinv64.as<double>(), r->bb,
                           q.rtol);
@@ -382,8 +403,41 @@ int true_residual(Server& S, Req* r, double& rel) {
   return PAFEM_OK;
 }
 
+// Mixed CG paused (or stopped on its recursive residual): replace the FP32
+// residual by the FP64 one; finish when that meets the tolerance (or maxit),
+// else complete the paused iteration's direction update and continue.
+void on_mixed_pause(Server& S, Req* r) {
+  const int64_t n = r->ndofs;
+  const int nb = reduce_blocks(n);
+  CgState* st = S.d_states.as<CgState>() + r->slot;
+  const float* dinv32 = r->op->d_dinv32.as<float>();
+  CgState hs{};
+  int rc = apply_impl<double>(r->op, r->x(), r->Ad(), PAFEM_APPLY_CONSTRAINED, nullptr, S.stream);
+  if (rc == PAFEM_OK &&
+      (launch_residual(r->b(), r->Ad(), r->r(), n, S.stream) != hipSuccess ||
+       launch_replace_residual(r->r(), dinv32, r->r32(), n, r->partials(), nb, st, S.stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, S.stream) != hipSuccess ||
+       hipStreamSynchronize(S.stream) != hipSuccess))
+    rc = PAFEM_ERR_HIP;
+  if (rc != PAFEM_OK) return finish(S, r, rc, false);
+  {
+    std::lock_guard<std::mutex> g(S.mu);
+    r->iterations = hs.iter;
+    r->outer += 1;
+    r->rel_res = r->bb > 0.0 ? std::sqrt(hs.rr / r->bb) : std::sqrt(hs.rr);
+  }
+  if (hs.done) {
+    const bool conv = hs.rr <= hs.rr_stop;
+    return finish(S, r, conv ? PAFEM_OK : PAFEM_ERR_NOT_CONVERGED, true);
+  }
+  if (launch_cg_pupdate<float>(r->dir32(), r->r32(), dinv32, n, st, S.stream) != hipSuccess)
+    finish(S, r, PAFEM_ERR_HIP, false);
+}
+
 // A request whose current CG has stopped: finish it, or take a refinement step.
 void on_cg_done(Server& S, Req* r, const CgState& st) {
+  if (r->mixed) return on_mixed_pause(S, r);
   if (!r->ir) {
     double rel = 0.0;
     int rc = true_residual(S, r, rel);
@@ -461,7 +515,7 @@ void engine(Server& S) {
         finish(S, r, rc, false);
         continue;
       }
-      if (r->ir) {
+      if (r->ir || r->mixed) {
         S.b32.members.push_back(r);
         S.b32.dirty = true;
       } else {
@@ -577,6 +631,7 @@ int pafem_server_submit(pafem_server* S, const pafem_request* req, uint64_t* tic
   r->verts.assign(req->verts_host, req->verts_host + nv);
   r->spec.verts_host = nullptr;
   r->ir = req->mode == PAFEM_SOLVE_IR_FP32;
+  r->mixed = req->mode == PAFEM_SOLVE_MIXED_FP32;
   r->ne = (int64_t)req->nx * req->ny * req->nz;
   r->ndofs = ((int64_t)req->nx * req->p + 1) * ((int64_t)req->ny * req->p + 1) *
              ((int64_t)req->nz * req->p + 1);

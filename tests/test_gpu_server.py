@@ -1,7 +1,9 @@
 """GPU tests of the continuous-batching solve server (through the C ABI).
 
-* every served solve reaches its residual target and agrees with the
-  single-solve path and with the CPU oracle;
+* every served solve (plain FP64, FP64 defect correction around FP32 inner
+  solves, and mixed FP32 CG with FP64 residual replacement) reaches its
+  residual target and agrees with the single-solve path and with the CPU
+  oracle;
 * a request's solution is bitwise the same alone and in a mix of other
   requests of different sizes and orders (deterministic E^T, fixed-order
   per-request reductions);
@@ -40,13 +42,17 @@ def _req(n, p, seed, mode, coef=0):
 
 
 def _submit(srv, r, **kw):
+    from paper_2402_15940_amd import pafem
+    if r["mode"] == pafem.SOLVE_MIXED_FP32:
+        kw = dict(kw, inner_rtol=0.1)  # the residual-replacement factor
     return srv.submit(r["nx"], r["ny"], r["nz"], r["p"], r["verts"], mode=r["mode"],
                       coef_kind=r["coef_kind"], coef_value=r["coef_value"], **kw)
 
 
 def test_served_solves_match_single_solves_and_oracle(pf, ctx):
     reqs = [_req(4, 2, 1, pf.SOLVE_PLAIN_FP64), _req(3, 4, 2, pf.SOLVE_IR_FP32),
-            _req(5, 3, 3, pf.SOLVE_IR_FP32, coef=pf.COEF_SINX), _req(2, 6, 4, pf.SOLVE_PLAIN_FP64)]
+            _req(5, 3, 3, pf.SOLVE_IR_FP32, coef=pf.COEF_SINX), _req(2, 6, 4, pf.SOLVE_PLAIN_FP64),
+            _req(4, 5, 5, pf.SOLVE_MIXED_FP32, coef=pf.COEF_SINX), _req(3, 7, 6, pf.SOLVE_MIXED_FP32)]
     srv = pf.Server(ctx, 8 << 30, max_slots=8, iters_per_round=5)
     tickets = [_submit(srv, r, rtol=1e-10, inner_rtol=1e-3) for r in reqs]
     srv.drain()
@@ -54,6 +60,8 @@ def test_served_solves_match_single_solves_and_oracle(pf, ctx):
         res = srv.poll(t)
         assert res["status"] == pf.REQ_DONE, res
         assert res["rel_res"] <= 1e-10 and res["t_done"] >= res["t_admit"] >= res["t_arrive"]
+        if r["mode"] == pf.SOLVE_MIXED_FP32:
+            assert res["outer_iterations"] >= 2  # residual replacements
         x = srv.solution(t)
         n = r["nx"]
         op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, r["verts"]), r["p"]), pf.DIFFUSION)
@@ -74,12 +82,12 @@ def test_served_solves_match_single_solves_and_oracle(pf, ctx):
     srv.close()
 
 
-@pytest.mark.parametrize("mode", ["plain", "ir"])
+@pytest.mark.parametrize("mode", ["plain", "ir", "mixed"])
 def test_result_is_bitwise_the_same_alone_and_in_a_mix(pf, ctx, mode):
-    m = pf.SOLVE_PLAIN_FP64 if mode == "plain" else pf.SOLVE_IR_FP32
+    m = {"plain": pf.SOLVE_PLAIN_FP64, "ir": pf.SOLVE_IR_FP32, "mixed": pf.SOLVE_MIXED_FP32}[mode]
     target = _req(4, 3, 11, m, coef=pf.COEF_SINX)
     others = [_req(3, 5, 12, pf.SOLVE_IR_FP32), _req(6, 2, 13, pf.SOLVE_PLAIN_FP64),
-              _req(2, 8, 14, pf.SOLVE_IR_FP32), _req(5, 4, 15, m)]
+              _req(2, 8, 14, pf.SOLVE_MIXED_FP32), _req(5, 4, 15, m)]
     srv = pf.Server(ctx, 8 << 30, max_slots=8, iters_per_round=4)
     t = _submit(srv, target, rtol=1e-10, inner_rtol=1e-3)
     srv.drain()
