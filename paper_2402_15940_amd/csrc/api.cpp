@@ -27,6 +27,24 @@ inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
     }                                    \
   } while (0)
 
+// The element kernels' 1D tables for every order, into constant memory of
+// the current device (each kernel source file holds its own copy).
+hipError_t upload_basis_tables() {
+  std::vector<double> t64(tab_words());
+  for (int p = 1; p <= kMaxP; ++p) {
+    const int n = p + 1, q = p + 2;
+    std::vector<double> nodes(n), pts(q), wts(q);
+    gll_nodes(p, nodes.data());
+    gauss_legendre(q, pts.data(), wts.data());
+    double* B = t64.data() + tab_off(p);
+    lagrange_tables(n, nodes.data(), q, pts.data(), B, B + q * n);
+  }
+  std::vector<float> t32(t64.begin(), t64.end());
+  hipError_t e = upload_tables_apply(t64.data(), t32.data(), t64.size());
+  if (e == hipSuccess) e = upload_tables_batched(t64.data(), t32.data(), t64.size());
+  return e;
+}
+
 int need_device(const Ctx* c) {
   if (c->host_only) {
     set_error("operation needs a GPU context (created with device >= 0)");
@@ -284,9 +302,10 @@ int pafem_ctx_create(int device, pafem_ctx** out) {
       return PAFEM_ERR_NO_DEVICE;
     }
     e = hipSetDevice(device);
+    if (e == hipSuccess) e = upload_basis_tables();
     if (e != hipSuccess) {
       delete c;
-      set_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+      set_error(std::string("device setup: ") + hipGetErrorString(e));
       return PAFEM_ERR_HIP;
     }
   }

@@ -50,6 +50,22 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
 constexpr int kWavesDiff64[] = {PAFEM_WAVES_DIFF_F64};
 
+// The 1D tables B[q][n], G[q][n] (q = p+2 Gauss-Legendre points, n = p+1 GLL
+// nodes) depend on p alone, so every element kernel reads them from constant
+// memory, [p = 1..8][B then G]: scalar loads the compiler may repeat anywhere
+// (no store can clobber them), whatever the origin of the other pointers.
+// Each translation unit that includes this header holds its own copy, filled
+// by its upload_tables_* function when a context is created.
+constexpr int kTabWords = tab_words();
+static __constant__ double c_tab64[kTabWords];
+static __constant__ float c_tab32[kTabWords];
+template <typename T>
+__device__ __forceinline__ const T* ctab(int p);
+template <>
+__device__ __forceinline__ const double* ctab<double>(int p) { return c_tab64 + tab_off(p); }
+template <>
+__device__ __forceinline__ const float* ctab<float>(int p) { return c_tab32 + tab_off(p); }
+
 __host__ __device__ constexpr int odd_up(int v) { return (v % 2 == 0) ? v + 1 : v; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -165,8 +181,8 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
   constexpr int N = C::N, QQ = C::QQ, L = C::L, R = C::R;
   constexpr int QQQ = Q * Q * Q;
-  const T* __restrict__ Bt = a.B;
-  const T* __restrict__ Gt = a.G;
+  const T* __restrict__ Bt = ctab<T>(P);
+  const T* __restrict__ Gt = ctab<T>(P) + Q * N;
 
   // stage-C role of this thread: z-line (qx, qy) of element slot sC
   const int sC = tid / QQ, rC = tid - sC * QQ;
@@ -368,7 +384,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   using C = Cfg<P, Q, T, PAFEM_MASS>;
   constexpr int N = C::N, QQ = C::QQ, L = C::L, R = C::R;
   constexpr int QQQ = Q * Q * Q;
-  const T* __restrict__ Bt = a.B;
+  const T* __restrict__ Bt = ctab<T>(P);
 
   const int sC = tid / QQ, rC = tid - sC * QQ;
   const int64_t eC = e0 + sC;

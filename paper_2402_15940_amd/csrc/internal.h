@@ -213,6 +213,21 @@ struct ApplyArgs {
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
 };
 
+// Offset of order p's tables in the concatenation [p = 1..8][B then G] (B, G
+// of shape [p+2][p+1]), and its total length.
+__host__ __device__ constexpr int tab_off(int p) {
+  int o = 0;
+  for (int k = 1; k < p; ++k) o += 2 * (k + 1) * (k + 3);
+  return o;
+}
+__host__ __device__ constexpr int tab_words() { return tab_off(kMaxP + 1); }
+
+// Fill the constant-memory 1D tables of the element kernels (one copy per
+// translation unit) on the current device: t64/t32 hold [p = 1..8][B then G]
+// with B, G of shape [p+2][p+1].
+hipError_t upload_tables_apply(const double* t64, const float* t32, size_t words);
+hipError_t upload_tables_batched(const double* t64, const float* t32, size_t words);
+
 // Internal output modes of the element pass: the full E-vector
 // [ne][(p+1)^3] (element results before assembly, pafem_op_apply_evector and
 // the stored-map deterministic E^T), and the same values with element rows
@@ -335,10 +350,13 @@ struct BatchHeader {
   int pad;
   int64_t total_work;
   int64_t total_chunks;
+  int64_t p_begin[kMaxP + 1], p_end[kMaxP + 1];  // work items of the entries of order p
 };
 
-// Elements per work item of the batched apply (q x q threads per element).
-__host__ __device__ constexpr int batch_elems(int q) { return kBatchThreads / (q * q); }
+// Elements per work item of the batched apply for order p in precision T (the
+// tuned elements-per-workgroup of the single-operator kernel).
+template <typename T>
+int batch_elems(int p);
 
 // K CG iterations for every active entry of the batch; grids are fixed so the
 // sequence can be captured once and replayed while the membership changes.

@@ -113,4 +113,11 @@ template hipError_t launch_apply<double>(int, int, int, int, int, const ApplyArg
 template hipError_t launch_apply<float>(int, int, int, int, int, const ApplyArgs<float>&,
                                         hipStream_t);
 
+hipError_t upload_tables_apply(const double* t64, const float* t32, size_t words) {
+  if (words != (size_t)apply::kTabWords) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(apply::c_tab64), t64, words * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(apply::c_tab32), t32, words * sizeof(float));
+  return e;
+}
+
 }  // namespace pafem

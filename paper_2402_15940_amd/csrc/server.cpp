@@ -187,7 +187,8 @@ BatchEntry<T> make_entry(Server& S, Req* r, int64_t work_begin, int64_t chunk_be
   e.ndofs = sp->ndofs;
   e.nchunks = r->nchunks();
   e.work_begin = work_begin;
-  e.work_end = work_begin + (sp->ne + batch_elems(q) - 1) / batch_elems(q);
+  const int ne_item = batch_elems<T>(sp->p);
+  e.work_end = work_begin + (sp->ne + ne_item - 1) / ne_item;
   e.chunk_begin = chunk_begin;
   e.chunk_end = chunk_begin + e.nchunks;
   e.st = S.d_states.as<CgState>() + r->slot;
@@ -223,15 +224,55 @@ BatchEntry<T> make_entry(Server& S, Req* r, int64_t work_begin, int64_t chunk_be
   return e;
 }
 
-// Rewrite the device table of a batch (members in admission order).
+// Device pointers of an entry as byte offsets from the device table `base`
+// (the batched kernels rebuild them from their table argument).
+template <typename P>
+P* offset_from(const void* base, P* p) {
+  return p == nullptr ? nullptr
+                      : (P*)(intptr_t)((const char*)p - (const char*)base);
+}
+template <typename T>
+BatchEntry<T> as_offsets(const void* base, BatchEntry<T> e) {
+  e.a.x = offset_from(base, e.a.x);
+  e.a.y = offset_from(base, e.a.y);
+  e.a.yE = offset_from(base, e.a.yE);
+  e.a.qd = offset_from(base, e.a.qd);
+  e.a.qd16 = offset_from(base, e.a.qd16);
+  e.a.E = offset_from(base, e.a.E);
+  e.a.ess_mask = offset_from(base, e.a.ess_mask);
+  e.a.B = offset_from(base, e.a.B);
+  e.a.G = offset_from(base, e.a.G);
+  e.a.skip = offset_from(base, e.a.skip);
+  e.x = offset_from(base, e.x);
+  e.r = offset_from(base, e.r);
+  e.dir = offset_from(base, e.dir);
+  e.Ad = offset_from(base, e.Ad);
+  e.dinv = offset_from(base, e.dinv);
+  e.st = offset_from(base, e.st);
+  e.partials = offset_from(base, e.partials);
+  e.x64 = offset_from(base, e.x64);
+  return e;
+}
+
+// Rewrite the device table of a batch: entries grouped by order p (each
+// order's element pass is its own launch over its range of work items), in
+// admission order within an order.
 template <typename T>
 int batch_upload(Server& S, Batch<T>& b) {
   int64_t w = 0, c = 0;
-  for (size_t i = 0; i < b.members.size(); ++i) {
-    b.h_entries[i] = make_entry<T>(S, b.members[i], w, c);
-    w = b.h_entries[i].work_end;
-    c = b.h_entries[i].chunk_end;
+  size_t i = 0;
+  for (int p = 1; p <= kMaxP; ++p) {
+    b.h_hdr->p_begin[p] = w;
+    for (Req* r : b.members) {
+      if (r->spec.p != p) continue;
+      b.h_entries[i] = as_offsets(b.d_entries.ptr, make_entry<T>(S, r, w, c));
+      w = b.h_entries[i].work_end;
+      c = b.h_entries[i].chunk_end;
+      ++i;
+    }
+    b.h_hdr->p_end[p] = w;
   }
+  b.h_hdr->p_begin[0] = b.h_hdr->p_end[0] = 0;
   b.h_hdr->n = (int)b.members.size();
   b.h_hdr->total_work = w;
   b.h_hdr->total_chunks = c;
@@ -403,41 +444,54 @@ int true_residual(Server& S, Req* r, double& rel) {
   return PAFEM_OK;
 }
 
-// Mixed CG paused (or stopped on its recursive residual): replace the FP32
-// residual by the FP64 one; finish when that meets the tolerance (or maxit),
-// else complete the paused iteration's direction update and continue.
-void on_mixed_pause(Server& S, Req* r) {
-  const int64_t n = r->ndofs;
-  const int nb = reduce_blocks(n);
-  CgState* st = S.d_states.as<CgState>() + r->slot;
-  const float* dinv32 = r->op->d_dinv32.as<float>();
-  CgState hs{};
-  int rc = apply_impl<double>(r->op, r->x(), r->Ad(), PAFEM_APPLY_CONSTRAINED, nullptr, S.stream);
-  if (rc == PAFEM_OK &&
-      (launch_residual(r->b(), r->Ad(), r->r(), n, S.stream) != hipSuccess ||
-       launch_replace_residual(r->r(), dinv32, r->r32(), n, r->partials(), nb, st, S.stream) !=
-           hipSuccess ||
-       hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, S.stream) != hipSuccess ||
-       hipStreamSynchronize(S.stream) != hipSuccess))
-    rc = PAFEM_ERR_HIP;
-  if (rc != PAFEM_OK) return finish(S, r, rc, false);
-  {
-    std::lock_guard<std::mutex> g(S.mu);
-    r->iterations = hs.iter;
-    r->outer += 1;
-    r->rel_res = r->bb > 0.0 ? std::sqrt(hs.rr / r->bb) : std::sqrt(hs.rr);
+// Mixed CGs paused (or stopped on their recursive residual): replace each
+// FP32 residual by the FP64 one (all requests' work enqueued, then one read of
+// the states); finish a request when that meets the tolerance (or maxit),
+// else complete its paused iteration's direction update and continue.
+void replace_residuals(Server& S, std::vector<Req*> reqs) {
+  std::vector<Req*> ok;
+  for (Req* r : reqs) {
+    const int64_t n = r->ndofs;
+    CgState* st = S.d_states.as<CgState>() + r->slot;
+    int rc = apply_impl<double>(r->op, r->x(), r->Ad(), PAFEM_APPLY_CONSTRAINED, nullptr,
+                                S.stream);
+    if (rc == PAFEM_OK &&
+        (launch_residual(r->b(), r->Ad(), r->r(), n, S.stream) != hipSuccess ||
+         launch_replace_residual(r->r(), r->op->d_dinv32.as<float>(), r->r32(), n,
+                                 r->partials(), reduce_blocks(n), st, S.stream) != hipSuccess))
+      rc = PAFEM_ERR_HIP;
+    if (rc != PAFEM_OK)
+      finish(S, r, rc, false);
+    else
+      ok.push_back(r);
   }
-  if (hs.done) {
-    const bool conv = hs.rr <= hs.rr_stop;
-    return finish(S, r, conv ? PAFEM_OK : PAFEM_ERR_NOT_CONVERGED, true);
+  if (ok.empty()) return;
+  if (hipMemcpyAsync(S.h_states, S.d_states.ptr, sizeof(CgState) * S.max_slots,
+                     hipMemcpyDeviceToHost, S.stream) != hipSuccess ||
+      hipStreamSynchronize(S.stream) != hipSuccess) {
+    for (Req* r : ok) finish(S, r, PAFEM_ERR_HIP, false);
+    return;
   }
-  if (launch_cg_pupdate<float>(r->dir32(), r->r32(), dinv32, n, st, S.stream) != hipSuccess)
-    finish(S, r, PAFEM_ERR_HIP, false);
+  for (Req* r : ok) {
+    const CgState hs = S.h_states[r->slot];
+    {
+      std::lock_guard<std::mutex> g(S.mu);
+      r->iterations = hs.iter;
+      r->outer += 1;
+      r->rel_res = r->bb > 0.0 ? std::sqrt(hs.rr / r->bb) : std::sqrt(hs.rr);
+    }
+    if (hs.done) {
+      finish(S, r, hs.rr <= hs.rr_stop ? PAFEM_OK : PAFEM_ERR_NOT_CONVERGED, true);
+    } else if (launch_cg_pupdate<float>(r->dir32(), r->r32(), r->op->d_dinv32.as<float>(),
+                                        r->ndofs, S.d_states.as<CgState>() + r->slot,
+                                        S.stream) != hipSuccess) {
+      finish(S, r, PAFEM_ERR_HIP, false);
+    }
+  }
 }
 
 // A request whose current CG has stopped: finish it, or take a refinement step.
 void on_cg_done(Server& S, Req* r, const CgState& st) {
-  if (r->mixed) return on_mixed_pause(S, r);
   if (!r->ir) {
     double rel = 0.0;
     int rc = true_residual(S, r, rel);
@@ -545,11 +599,16 @@ void engine(Server& S) {
       for (Req* r : all) finish(S, r, rc, false);
       continue;
     }
-    std::vector<Req*> cur = S.active;
+    std::vector<Req*> cur = S.active, paused;
     for (Req* r : cur) {
-      const CgState& st = S.h_states[r->slot];
-      if (st.done) on_cg_done(S, r, st);
+      const CgState st = S.h_states[r->slot];
+      if (!st.done) continue;
+      if (r->mixed)
+        paused.push_back(r);
+      else
+        on_cg_done(S, r, st);
     }
+    if (!paused.empty()) replace_residuals(S, paused);
   }
 }
 

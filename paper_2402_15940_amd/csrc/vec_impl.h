@@ -79,11 +79,13 @@ __device__ __forceinline__ void final_sums(const double* partials, int nb, int n
 // (element, local node) order (the order of the stored map's CSR sum, so the
 // forms agree bitwise); constrained essential rows take x[i] (or 0).  The up
 // to eight contributions are loaded together.
-template <typename T, bool XROWS = false>
+// PC > 0 fixes the order at compile time (divisions by a constant).
+template <typename T, bool XROWS = false, int PC = 0>
 __device__ __forceinline__ void gather_lattice_ijk(const T* __restrict__ yE, int nx, int ny,
-                                                   int nz, int p, int constrained, int accumulate,
-                                                   const T* __restrict__ x, T* __restrict__ y,
-                                                   int I, int J, int K) {
+                                                   int nz, int p_rt, int constrained,
+                                                   int accumulate, const T* __restrict__ x,
+                                                   T* __restrict__ y, int I, int J, int K) {
+  const int p = PC > 0 ? PC : p_rt;
   const int Lx = nx * p + 1, Ly = ny * p + 1, Lz = nz * p + 1;
   const int64_t i = I + (int64_t)Lx * (J + (int64_t)Ly * K);
   T acc = 0;
@@ -122,16 +124,17 @@ __device__ __forceinline__ void gather_lattice_ijk(const T* __restrict__ yE, int
   y[i] = accumulate ? y[i] + acc : acc;
 }
 
-// The same at linear lattice index i (below the node count).
-template <typename T, bool XROWS = false>
+// The same at linear lattice index i (below the node count, < 2^31).
+template <typename T, bool XROWS = false, int PC = 0>
 __device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, int nx, int ny,
-                                                    int nz, int p, int constrained,
+                                                    int nz, int p_rt, int constrained,
                                                     int accumulate, const T* __restrict__ x,
                                                     T* __restrict__ y, int64_t i) {
+  const int p = PC > 0 ? PC : p_rt;
   const int Lx = nx * p + 1, Ly = ny * p + 1;
-  const int r = (int)(i / Lx);
-  gather_lattice_ijk<T, XROWS>(yE, nx, ny, nz, p, constrained, accumulate, x, y,
-                               (int)(i - (int64_t)r * Lx), r % Ly, r / Ly);
+  const int ii = (int)i, r = ii / Lx;
+  gather_lattice_ijk<T, XROWS, PC>(yE, nx, ny, nz, p, constrained, accumulate, x, y,
+                                   ii - r * Lx, r % Ly, r / Ly);
 }
 
 }  // namespace vec
