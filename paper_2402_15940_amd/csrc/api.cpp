@@ -33,11 +33,33 @@ hipError_t upload_basis_tables() {
   std::vector<double> t64(tab_words());
   for (int p = 1; p <= kMaxP; ++p) {
     const int n = p + 1, q = p + 2;
+    const int nh = n / 2, nhe = n - nh, qh = q / 2, qhe = q - qh;
     std::vector<double> nodes(n), pts(q), wts(q);
     gll_nodes(p, nodes.data());
     gauss_legendre(q, pts.data(), wts.data());
     double* B = t64.data() + tab_off(p);
     lagrange_tables(n, nodes.data(), q, pts.data(), B, B + q * n);
+    // mirror-split tables of B (t = 0) and G (t = 1): sums and differences of
+    // mirrored entries, halved; the middle node / point enters once
+    for (int t = 0; t < 2; ++t) {
+      const double* T = B + t * q * n;
+      double* Pf = B + 2 * q * n + t * mir_words(p);
+      double* Mf = Pf + qhe * nhe;
+      double* Pt = Mf + qhe * nh;
+      double* Mt = Pt + nhe * qhe;
+      for (int j = 0; j < qhe; ++j)
+        for (int i = 0; i < nhe; ++i) {
+          const double a = T[j * n + i], b = T[j * n + (n - 1 - i)];
+          Pf[j * nhe + i] = i < nh ? 0.5 * (a + b) : a;
+          if (i < nh) Mf[j * nh + i] = 0.5 * (a - b);
+        }
+      for (int i = 0; i < nhe; ++i)
+        for (int k = 0; k < qhe; ++k) {
+          const double a = T[k * n + i], b = T[(q - 1 - k) * n + i];
+          Pt[i * qhe + k] = k < qh ? 0.5 * (a + b) : a;
+          if (k < qh) Mt[i * qh + k] = 0.5 * (a - b);
+        }
+    }
   }
   std::vector<float> t32(t64.begin(), t64.end());
   hipError_t e = upload_tables_apply(t64.data(), t32.data(), t64.size());

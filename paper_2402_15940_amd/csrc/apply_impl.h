@@ -66,6 +66,62 @@ __device__ __forceinline__ const double* ctab<double>(int p) { return c_tab64 + 
 template <>
 __device__ __forceinline__ const float* ctab<float>(int p) { return c_tab32 + tab_off(p); }
 
+// ---- mirror split of the 1D contractions ----------------------------------
+// The GLL nodes and the Gauss points lie symmetrically about the element
+// centre, so T[Q-1-q][N-1-i] = S T[q][i] with S = +1 for B and -1 for G.
+// With e_i = u_i + u_{N-1-i}, o_i = u_i - u_{N-1-i} (i < N/2; for odd N, e
+// also carries the middle value), a contraction y_q = sum_i T[q][i] u_i is
+//   E_q = sum_i P[q][i] e_i,  O_q = sum_i M[q][i] o_i   (q < ceil(Q/2))
+//   y_q = E_q + O_q,  y_{Q-1-q} = S (E_q - O_q)          (q < Q/2)
+// with P, M the halved sums and differences of mirrored table entries: about
+// half the multiply-adds of the plain contraction.  The transposed
+// contraction (over the points, to the nodes) has the same form with the
+// roles of N and Q exchanged.
+template <int N>
+struct Mir {
+  static constexpr int H = N / 2;        // mirror pairs
+  static constexpr int HE = N - N / 2;   // pairs, and the middle when N is odd
+};
+
+// The split tables of order P for table t (0: B, 1: G), in constant memory.
+template <typename T, int P>
+struct SplitTab {
+  static constexpr int N = P + 1, Q = P + 2;
+  static constexpr int NH = Mir<N>::H, NHE = Mir<N>::HE, QH = Mir<Q>::H, QHE = Mir<Q>::HE;
+  __device__ static const T* Pf(int t) { return ctab<T>(P) + 2 * Q * N + t * mir_words(P); }
+  __device__ static const T* Mf(int t) { return Pf(t) + QHE * NHE; }
+  __device__ static const T* Pt(int t) { return Mf(t) + QHE * NH; }
+  __device__ static const T* Mt(int t) { return Pt(t) + NHE * QHE; }
+};
+
+template <int N, typename T>
+__device__ __forceinline__ void mirror(const T (&u)[N], T (&e)[Mir<N>::HE], T (&o)[Mir<N>::H]) {
+#pragma unroll
+  for (int i = 0; i < Mir<N>::H; ++i) {
+    e[i] = u[i] + u[N - 1 - i];
+    o[i] = u[i] - u[N - 1 - i];
+  }
+  if (N % 2) e[Mir<N>::H] = u[Mir<N>::H];
+}
+
+// y[NO] from the split (e, o) of a vector of length NI; Pt [OHE][IHE], Mt [OHE][IH].
+template <int NI, int NO, int S, typename T>
+__device__ __forceinline__ void contract(const T* __restrict__ Ptab, const T* __restrict__ Mtab,
+                                         const T (&e)[Mir<NI>::HE], const T (&o)[Mir<NI>::H],
+                                         T (&y)[NO]) {
+  constexpr int IH = Mir<NI>::H, IHE = Mir<NI>::HE, OH = Mir<NO>::H, OHE = Mir<NO>::HE;
+#pragma unroll
+  for (int j = 0; j < OHE; ++j) {
+    T E = 0, O = 0;
+#pragma unroll
+    for (int i = 0; i < IHE; ++i) E = fma(Ptab[j * IHE + i], e[i], E);
+#pragma unroll
+    for (int i = 0; i < IH; ++i) O = fma(Mtab[j * IH + i], o[i], O);
+    y[j] = E + O;
+    if (j < OH) y[NO - 1 - j] = S > 0 ? E - O : O - E;
+  }
+}
+
 __host__ __device__ constexpr int odd_up(int v) { return (v % 2 == 0) ? v + 1 : v; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -181,8 +237,8 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
   constexpr int N = C::N, QQ = C::QQ, L = C::L, R = C::R;
   constexpr int QQQ = Q * Q * Q;
-  const T* __restrict__ Bt = ctab<T>(P);
-  const T* __restrict__ Gt = ctab<T>(P) + Q * N;
+  using ST = SplitTab<T, P>;
+  constexpr int HN = Mir<N>::HE, LN = Mir<N>::H, HQ = Mir<Q>::HE, LQ = Mir<Q>::H;
 
   // stage-C role of this thread: z-line (qx, qy) of element slot sC
   const int sC = tid / QQ, rC = tid - sC * QQ;
@@ -240,16 +296,14 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int b = 0; b < N; ++b)  // a select, not a branch: no early wait on the loads
       u[b] = (a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) ? T(0) : u[b];
     T* reg = smem + sA * L + (cA * Q) * R + aA;  // region (c, qy) at + qy*R
+    T ue[HN], uo[LN], tb[Q], tg[Q];
+    mirror<N>(u, ue, uo);
+    contract<N, Q, 1>(ST::Pf(0), ST::Mf(0), ue, uo, tb);
+    contract<N, Q, -1>(ST::Pf(1), ST::Mf(1), ue, uo, tg);
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {
-      T tb = 0, tg = 0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        tb = fma(Bt[qy * N + b], u[b], tb);
-        tg = fma(Gt[qy * N + b], u[b], tg);
-      }
-      reg[qy * R] = tb;
-      reg[qy * R + N] = tg;
+      reg[qy * R] = tb[qy];
+      reg[qy * R + N] = tg[qy];
     }
   }
   __syncthreads();
@@ -266,18 +320,17 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       tb[i] = reg[i];
       tg[i] = reg[N + i];
     }
+    T be[HN], bo[LN], ge[HN], go[LN], bb[Q], gb[Q], bg[Q];  // factors (x, y): (B,B) (G,B) (B,G)
+    mirror<N>(tb, be, bo);
+    mirror<N>(tg, ge, go);
+    contract<N, Q, 1>(ST::Pf(0), ST::Mf(0), be, bo, bb);
+    contract<N, Q, -1>(ST::Pf(1), ST::Mf(1), be, bo, gb);
+    contract<N, Q, 1>(ST::Pf(0), ST::Mf(0), ge, go, bg);
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) {
-      T bb = 0, gb = 0, bg = 0;  // factors (x, y): (B,B) (G,B) (B,G)
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        bb = fma(Bt[qx * N + i], tb[i], bb);
-        gb = fma(Gt[qx * N + i], tb[i], gb);
-        bg = fma(Bt[qx * N + i], tg[i], bg);
-      }
-      reg[qx] = bb;
-      reg[Q + qx] = gb;
-      reg[2 * Q + qx] = bg;
+      reg[qx] = bb[qx];
+      reg[Q + qx] = gb[qx];
+      reg[2 * Q + qx] = bg[qx];
     }
   }
   __syncthreads();
@@ -292,33 +345,82 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       igb[c] = reg0[c * Q * R + Q];
       ibg[c] = reg0[c * Q * R + 2 * Q];
     }
-    T w1[N], w2[N], w3[N];
+    // mirror pairs of points (qz, Q-1-qz) are handled together: the split
+    // forward contraction gives the reference gradient at both, D is applied
+    // at both, and their sum and difference feed the split transposed one
+    T bbe[HN], bbo[LN], gbe[HN], gbo[LN], bge[HN], bgo[LN];
+    mirror<N>(ibb, bbe, bbo);
+    mirror<N>(igb, gbe, gbo);
+    mirror<N>(ibg, bge, bgo);
+    const T* PfB = ST::Pf(0);
+    const T* MfB = ST::Mf(0);
+    const T* PfG = ST::Pf(1);
+    const T* MfG = ST::Mf(1);
+    const T* PtB = ST::Pt(0);
+    const T* MtB = ST::Mt(0);
+    const T* PtG = ST::Pt(1);
+    const T* MtG = ST::Mt(1);
+    T E1[HN], O1[HN], E2[HN], O2[HN], E3[HN], O3[HN];
 #pragma unroll
-    for (int c = 0; c < N; ++c) w1[c] = w2[c] = w3[c] = 0;
+    for (int i = 0; i < HN; ++i) E1[i] = O1[i] = E2[i] = O2[i] = E3[i] = O3[i] = 0;
 #pragma unroll
-    for (int qz = 0; qz < Q; ++qz) {
-      T gx = 0, gy = 0, gz = 0;
+    for (int k = 0; k < HQ; ++k) {
+      T ex = 0, ox = 0, ey = 0, oy = 0, ez = 0, oz = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        gx = fma(Bt[qz * N + c], igb[c], gx);
-        gy = fma(Bt[qz * N + c], ibg[c], gy);
-        gz = fma(Gt[qz * N + c], ibb[c], gz);
+      for (int i = 0; i < HN; ++i) {
+        ex = fma(PfB[k * HN + i], gbe[i], ex);
+        ey = fma(PfB[k * HN + i], bge[i], ey);
+        ez = fma(PfG[k * HN + i], bbe[i], ez);
       }
-      const T vx = fma(dq[0][qz], gx, fma(dq[1][qz], gy, dq[2][qz] * gz));
-      const T vy = fma(dq[1][qz], gx, fma(dq[3][qz], gy, dq[4][qz] * gz));
-      const T vz = fma(dq[2][qz], gx, fma(dq[4][qz], gy, dq[5][qz] * gz));
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        w1[c] = fma(Bt[qz * N + c], vx, w1[c]);
-        w2[c] = fma(Bt[qz * N + c], vy, w2[c]);
-        w3[c] = fma(Gt[qz * N + c], vz, w3[c]);
+      for (int i = 0; i < LN; ++i) {
+        ox = fma(MfB[k * LN + i], gbo[i], ox);
+        oy = fma(MfB[k * LN + i], bgo[i], oy);
+        oz = fma(MfG[k * LN + i], bbo[i], oz);
+      }
+      // point k
+      const T gx0 = ex + ox, gy0 = ey + oy, gz0 = ez + oz;
+      const T vx0 = fma(dq[0][k], gx0, fma(dq[1][k], gy0, dq[2][k] * gz0));
+      const T vy0 = fma(dq[1][k], gx0, fma(dq[3][k], gy0, dq[4][k] * gz0));
+      const T vz0 = fma(dq[2][k], gx0, fma(dq[4][k], gy0, dq[5][k] * gz0));
+      if (k < LQ) {
+        // its mirror Q-1-k
+        const int m = Q - 1 - k;
+        const T gx1 = ex - ox, gy1 = ey - oy, gz1 = oz - ez;
+        const T vx1 = fma(dq[0][m], gx1, fma(dq[1][m], gy1, dq[2][m] * gz1));
+        const T vy1 = fma(dq[1][m], gx1, fma(dq[3][m], gy1, dq[4][m] * gz1));
+        const T vz1 = fma(dq[2][m], gx1, fma(dq[4][m], gy1, dq[5][m] * gz1));
+        const T fx = vx0 + vx1, gxd = vx0 - vx1, fy = vy0 + vy1, gyd = vy0 - vy1;
+        const T fz = vz0 + vz1, gzd = vz0 - vz1;
+#pragma unroll
+        for (int i = 0; i < HN; ++i) {
+          E1[i] = fma(PtB[i * HQ + k], fx, E1[i]);
+          O1[i] = fma(MtB[i * LQ + k], gxd, O1[i]);
+          E2[i] = fma(PtB[i * HQ + k], fy, E2[i]);
+          O2[i] = fma(MtB[i * LQ + k], gyd, O2[i]);
+          E3[i] = fma(PtG[i * HQ + k], fz, E3[i]);
+          O3[i] = fma(MtG[i * LQ + k], gzd, O3[i]);
+        }
+      } else {  // the middle point of an odd Q
+#pragma unroll
+        for (int i = 0; i < HN; ++i) {
+          E1[i] = fma(PtB[i * HQ + k], vx0, E1[i]);
+          E2[i] = fma(PtB[i * HQ + k], vy0, E2[i]);
+          E3[i] = fma(PtG[i * HQ + k], vz0, E3[i]);
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      reg0[c * Q * R] = w1[c];
-      reg0[c * Q * R + Q] = w2[c];
-      reg0[c * Q * R + 2 * Q] = w3[c];
+    for (int i = 0; i < HN; ++i) {
+      reg0[i * Q * R] = E1[i] + O1[i];
+      reg0[i * Q * R + Q] = E2[i] + O2[i];
+      reg0[i * Q * R + 2 * Q] = E3[i] + O3[i];
+      if (i < LN) {
+        const int m = N - 1 - i;
+        reg0[m * Q * R] = E1[i] - O1[i];
+        reg0[m * Q * R + Q] = E2[i] - O2[i];
+        reg0[m * Q * R + 2 * Q] = O3[i] - E3[i];
+      }
     }
   }
   __syncthreads();
@@ -335,16 +437,17 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       w2[qx] = reg[Q + qx];
       w3[qx] = reg[2 * Q + qx];
     }
+    T f1[HQ], g1[LQ], f2[HQ], g2[LQ], f3[HQ], g3[LQ], s1[N], s3[N], s2[N];
+    mirror<Q>(w1, f1, g1);
+    mirror<Q>(w2, f2, g2);
+    mirror<Q>(w3, f3, g3);
+    contract<Q, N, -1>(ST::Pt(1), ST::Mt(1), f1, g1, s1);
+    contract<Q, N, 1>(ST::Pt(0), ST::Mt(0), f3, g3, s3);
+    contract<Q, N, 1>(ST::Pt(0), ST::Mt(0), f2, g2, s2);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      T s13 = 0, s2 = 0;
-#pragma unroll
-      for (int qx = 0; qx < Q; ++qx) {
-        s13 = fma(Gt[qx * N + i], w1[qx], fma(Bt[qx * N + i], w3[qx], s13));
-        s2 = fma(Bt[qx * N + i], w2[qx], s2);
-      }
-      reg[i] = s13;
-      reg[N + i] = s2;
+      reg[i] = s1[i] + s3[i];
+      reg[N + i] = s2[i];
     }
   }
   __syncthreads();
@@ -361,14 +464,13 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
     // the whole line is contracted before the first store: a global store
     // may alias the tables as far as the compiler can tell, and would force
     // every later table read onto the vector memory path
-    T acc[N];
+    T f13[HQ], g13[LQ], f2[HQ], g2[LQ], a13[N], a2[N], acc[N];
+    mirror<Q>(X13, f13, g13);
+    mirror<Q>(X2, f2, g2);
+    contract<Q, N, 1>(ST::Pt(0), ST::Mt(0), f13, g13, a13);
+    contract<Q, N, -1>(ST::Pt(1), ST::Mt(1), f2, g2, a2);
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      acc[b] = 0;
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy)
-        acc[b] = fma(Bt[qy * N + b], X13[qy], fma(Gt[qy * N + b], X2[qy], acc[b]));
-    }
+    for (int b = 0; b < N; ++b) acc[b] = a13[b] + a2[b];
     Restrict<P, IDX, T> E;
     E.init(a, eA);
     store_line<P, SCATTER, IDX>(a, E, eA, aA, cA, acc);
@@ -384,7 +486,8 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   using C = Cfg<P, Q, T, PAFEM_MASS>;
   constexpr int N = C::N, QQ = C::QQ, L = C::L, R = C::R;
   constexpr int QQQ = Q * Q * Q;
-  const T* __restrict__ Bt = ctab<T>(P);
+  using ST = SplitTab<T, P>;
+  constexpr int HN = Mir<N>::HE, LN = Mir<N>::H, HQ = Mir<Q>::HE, LQ = Mir<Q>::H;
 
   const int sC = tid / QQ, rC = tid - sC * QQ;
   const int64_t eC = e0 + sC;
@@ -421,13 +524,11 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     for (int b = 0; b < N; ++b)
       u[b] = (a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) ? T(0) : u[b];
     T* reg = smem + sA * L + (cA * Q) * R + aA;
+    T ue[HN], uo[LN], tb[Q];
+    mirror<N>(u, ue, uo);
+    contract<N, Q, 1>(ST::Pf(0), ST::Mf(0), ue, uo, tb);
 #pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-      T tb = 0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) tb = fma(Bt[qy * N + b], u[b], tb);
-      reg[qy * R] = tb;
-    }
+    for (int qy = 0; qy < Q; ++qy) reg[qy * R] = tb[qy];
   }
   __syncthreads();
 
@@ -436,53 +537,66 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   const int qyB = rB % Q, cB = rB / Q;
   if (actB) {
     T* reg = smem + sB * L + (cB * Q + qyB) * R;
-    T tb[N];
+    T tb[N], be[HN], bo[LN], bb[Q];
 #pragma unroll
     for (int i = 0; i < N; ++i) tb[i] = reg[i];
+    mirror<N>(tb, be, bo);
+    contract<N, Q, 1>(ST::Pf(0), ST::Mf(0), be, bo, bb);
 #pragma unroll
-    for (int qx = 0; qx < Q; ++qx) {
-      T bb = 0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) bb = fma(Bt[qx * N + i], tb[i], bb);
-      reg[qx] = bb;
-    }
+    for (int qx = 0; qx < Q; ++qx) reg[qx] = bb[qx];
   }
   __syncthreads();
 
   if (actC) {
     T* reg0 = smem + sC * L + qyC * R + qxC;
-    T in[N], w[N];
+    T in[N], ie[HN], io[LN], E[HN], O[HN];
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      in[c] = reg0[c * Q * R];
-      w[c] = 0;
+    for (int c = 0; c < N; ++c) in[c] = reg0[c * Q * R];
+    mirror<N>(in, ie, io);
+    const T* PfB = ST::Pf(0);
+    const T* MfB = ST::Mf(0);
+    const T* PtB = ST::Pt(0);
+    const T* MtB = ST::Mt(0);
+#pragma unroll
+    for (int i = 0; i < HN; ++i) E[i] = O[i] = 0;
+#pragma unroll
+    for (int k = 0; k < HQ; ++k) {  // mirror pairs of points (see diff_elements)
+      T e = 0, o = 0;
+#pragma unroll
+      for (int i = 0; i < HN; ++i) e = fma(PfB[k * HN + i], ie[i], e);
+#pragma unroll
+      for (int i = 0; i < LN; ++i) o = fma(MfB[k * LN + i], io[i], o);
+      const T v0 = dq[k] * (e + o);
+      if (k < LQ) {
+        const T v1 = dq[Q - 1 - k] * (e - o);
+        const T f = v0 + v1, g = v0 - v1;
+#pragma unroll
+        for (int i = 0; i < HN; ++i) {
+          E[i] = fma(PtB[i * HQ + k], f, E[i]);
+          O[i] = fma(MtB[i * LQ + k], g, O[i]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < HN; ++i) E[i] = fma(PtB[i * HQ + k], v0, E[i]);
+      }
     }
 #pragma unroll
-    for (int qz = 0; qz < Q; ++qz) {
-      T uq = 0;
-#pragma unroll
-      for (int c = 0; c < N; ++c) uq = fma(Bt[qz * N + c], in[c], uq);
-      const T v = dq[qz] * uq;
-#pragma unroll
-      for (int c = 0; c < N; ++c) w[c] = fma(Bt[qz * N + c], v, w[c]);
+    for (int i = 0; i < HN; ++i) {
+      reg0[i * Q * R] = E[i] + O[i];
+      if (i < LN) reg0[(N - 1 - i) * Q * R] = E[i] - O[i];
     }
-#pragma unroll
-    for (int c = 0; c < N; ++c) reg0[c * Q * R] = w[c];
   }
   __syncthreads();
 
   if (actB) {
     T* reg = smem + sB * L + (cB * Q + qyB) * R;
-    T w[Q];
+    T w[Q], f[HQ], g[LQ], s1[N];
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) w[qx] = reg[qx];
+    mirror<Q>(w, f, g);
+    contract<Q, N, 1>(ST::Pt(0), ST::Mt(0), f, g, s1);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      T s1 = 0;
-#pragma unroll
-      for (int qx = 0; qx < Q; ++qx) s1 = fma(Bt[qx * N + i], w[qx], s1);
-      reg[i] = s1;
-    }
+    for (int i = 0; i < N; ++i) reg[i] = s1[i];
   }
   __syncthreads();
 
@@ -491,13 +605,9 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     T W[Q];
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) W[qy] = reg[qy * R];
-    T acc[N];  // contracted before the first store (see diff_elements)
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      acc[b] = 0;
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy) acc[b] = fma(Bt[qy * N + b], W[qy], acc[b]);
-    }
+    T f[HQ], g[LQ], acc[N];  // contracted before the first store (see diff_elements)
+    mirror<Q>(W, f, g);
+    contract<Q, N, 1>(ST::Pt(0), ST::Mt(0), f, g, acc);
     Restrict<P, IDX, T> E;
     E.init(a, eA);
     store_line<P, SCATTER, IDX>(a, E, eA, aA, cA, acc);

@@ -213,18 +213,27 @@ struct ApplyArgs {
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
 };
 
-// Offset of order p's tables in the concatenation [p = 1..8][B then G] (B, G
-// of shape [p+2][p+1]), and its total length.
+// Tables of the element kernels for order p (n = p+1 nodes, q = p+2 points):
+// B and G [q][n], then, for B and for G, the mirror-split tables of the
+// contractions (see apply_impl.h), with nh = n/2, nhe = n - n/2 and the same
+// for q:  Pf [qhe][nhe], Mf [qhe][nh]   (over the nodes, to the points)
+//         Pt [nhe][qhe], Mt [nhe][qh]   (over the points, to the nodes)
+__host__ __device__ constexpr int mir_words(int p) {
+  const int n = p + 1, q = p + 2, nh = n / 2, nhe = n - n / 2, qh = q / 2, qhe = q - q / 2;
+  return qhe * nhe + qhe * nh + nhe * qhe + nhe * qh;
+}
+__host__ __device__ constexpr int tab_len(int p) { return 2 * (p + 2) * (p + 1) + 2 * mir_words(p); }
+// Offset of order p's tables in the concatenation over p = 1..8, and its length.
 __host__ __device__ constexpr int tab_off(int p) {
   int o = 0;
-  for (int k = 1; k < p; ++k) o += 2 * (k + 1) * (k + 3);
+  for (int k = 1; k < p; ++k) o += tab_len(k);
   return o;
 }
 __host__ __device__ constexpr int tab_words() { return tab_off(kMaxP + 1); }
 
-// Fill the constant-memory 1D tables of the element kernels (one copy per
-// translation unit) on the current device: t64/t32 hold [p = 1..8][B then G]
-// with B, G of shape [p+2][p+1].
+// Fill the constant-memory tables of the element kernels (one copy per
+// translation unit) on the current device: t64/t32 hold the tables of
+// p = 1..8 at tab_off(p).
 hipError_t upload_tables_apply(const double* t64, const float* t32, size_t words);
 hipError_t upload_tables_batched(const double* t64, const float* t32, size_t words);
 
