@@ -224,6 +224,32 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   return PAFEM_OK;
 }
 
+template <typename T>
+int apply_elements_dot(Op* op, const T* p, const int* skip, hipStream_t s, int qprec,
+                       int* nparts) {
+  Space* sp = op->space;
+  if (op->scatter_mode != PAFEM_SCATTER_DETERMINISTIC || op->index_mode != PAFEM_INDEX_LATTICE) {
+    set_error("internal: the fused CG element pass needs the lattice numbering");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  const int64_t nb = element_blocks(op->kind, sp->p, sp->ne, !std::is_same<T, double>::value);
+  if (nb <= 0 || nb > INT32_MAX) {
+    set_error("internal: element workgroup count out of range");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, sp->p + 1) * sizeof(double)));
+  PAFEM_TRY(op->d_gpart.ensure((size_t)nb * sizeof(double)));
+  ApplyArgs<T> a =
+      make_args<T>(op, p, nullptr, op->d_evec.as<T>(), PAFEM_APPLY_CONSTRAINED, skip, qprec);
+  a.dot_part = op->d_gpart.as<double>();
+  PAFEM_TRY_HIP(
+      launch_apply<T>(op->kind, sp->p, op->q, kScatterXRowsDot, PAFEM_INDEX_LATTICE, a, s));
+  *nparts = (int)nb;
+  return PAFEM_OK;
+}
+template int apply_elements_dot<double>(Op*, const double*, const int*, hipStream_t, int, int*);
+template int apply_elements_dot<float>(Op*, const float*, const int*, hipStream_t, int, int*);
+
 // y = E^T yE over every node (constrained: essential rows set to 0), in the
 // op's restriction mode.
 int gather_full(Op* op, const double* yE, int constrained, double* y, hipStream_t s) {

@@ -42,7 +42,7 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 // elements per workgroup by q, and the waves per SIMD the register allocation
 // must leave room for, by p, for the FP64 diffusion kernel.
 #ifndef PAFEM_NE_BY_Q
-#define PAFEM_NE_BY_Q 1, 1, 1, 7, 4, 5, 7, 5, 1, 3, 2
+#define PAFEM_NE_BY_Q 1, 1, 1, 7, 4, 5, 7, 5, 1, 3, 1
 #endif
 #ifndef PAFEM_WAVES_DIFF_F64
 #define PAFEM_WAVES_DIFF_F64 1, 1, 1, 1, 4, 1, 1, 1, 1
@@ -205,7 +205,7 @@ template <int P, int SCATTER, int IDX, typename T>
 __device__ __forceinline__ void store_line(const ApplyArgs<T>& a, const Restrict<P, IDX, T>& E,
                                            int64_t e, int aa, int c, const T (&acc)[P + 1]) {
   constexpr int N = P + 1;
-  if constexpr (SCATTER == kScatterXRows) {
+  if constexpr (SCATTER == kScatterXRows || SCATTER == kScatterXRowsDot) {
     static_assert(IDX == PAFEM_INDEX_LATTICE, "x-interleaved rows need the lattice numbering");
     T* out = a.yE + xrows_index(a.nx, a.ny, N, E.ex, E.ey, E.ez, aa, 0, c);
     const int stride = a.nx * xrows_width(N);
@@ -224,6 +224,40 @@ __device__ __forceinline__ void store_line(const ApplyArgs<T>& a, const Restrict
   }
 }
 
+// Partials of x . (A x) for CG (kScatterXRowsDot).  With u = B x_e at the
+// quadrature points of an element (x masked on the essential dofs) and D the
+// pointwise data, x_e . (A_e x_e) = sum_q u_q . (D_q u_q): stage C has both
+// factors in registers, so the dot product needs no pass over A x.  The
+// constrained operator is the identity on essential rows, which adds x_i^2
+// for each of them; stage A sees x_i before the mask, and the element that
+// owns the node counts it (lowest local index in each direction, the last
+// element keeping its far face).
+template <int P, typename T>
+__device__ __forceinline__ bool owns_node(const Restrict<P, PAFEM_INDEX_LATTICE, T>& E,
+                                          const ApplyArgs<T>& a, int aa, int b, int c) {
+  return (aa < P || E.ex == a.nx - 1) && (b < P || E.ey == a.ny - 1) &&
+         (c < P || E.ez == a.nz - 1);
+}
+
+// Sum of v over the workgroup into a.dot_part[block]; every thread calls it.
+__device__ __forceinline__ void workgroup_dot(double* dot_part, double v, int64_t block) {
+  __shared__ double red[16];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+  if (nw == 1) {
+    if (lane == 0) dot_part[block] = v;
+    return;
+  }
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    dot_part[block] = t;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // diffusion: y_e = sum_ij G_i^T S_ij G_j x_e, S = w k adj(J) adj(J)^T / detJ
 // stored as the 6 upper-triangle entries per quadrature point.
@@ -239,6 +273,9 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   constexpr int QQQ = Q * Q * Q;
   using ST = SplitTab<T, P>;
   constexpr int HN = Mir<N>::HE, LN = Mir<N>::H, HQ = Mir<Q>::HE, LQ = Mir<Q>::H;
+
+  constexpr bool DOT = SCATTER == kScatterXRowsDot;
+  double vd = 0.0;  // this thread's share of x . (A x) (DOT only)
 
   // stage-C role of this thread: z-line (qx, qy) of element slot sC
   const int sC = tid / QQ, rC = tid - sC * QQ;
@@ -293,8 +330,14 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   // ---- stage A: y contraction ----
   if (actA) {
 #pragma unroll
-    for (int b = 0; b < N; ++b)  // a select, not a branch: no early wait on the loads
-      u[b] = (a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) ? T(0) : u[b];
+    for (int b = 0; b < N; ++b) {  // a select, not a branch: no early wait on the loads
+      const bool es = a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA);
+      if constexpr (DOT) {
+        const double ub = (es && owns_node<P>(EA, a, aA, b, cA)) ? (double)u[b] : 0.0;
+        vd = fma(ub, ub, vd);
+      }
+      u[b] = es ? T(0) : u[b];
+    }
     T* reg = smem + sA * L + (cA * Q) * R + aA;  // region (c, qy) at + qy*R
     T ue[HN], uo[LN], tb[Q], tg[Q];
     mirror<N>(u, ue, uo);
@@ -363,6 +406,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
     T E1[HN], O1[HN], E2[HN], O2[HN], E3[HN], O3[HN];
 #pragma unroll
     for (int i = 0; i < HN; ++i) E1[i] = O1[i] = E2[i] = O2[i] = E3[i] = O3[i] = 0;
+    T vq = 0;  // sum over this z-line of grad . (D grad) (DOT only)
 #pragma unroll
     for (int k = 0; k < HQ; ++k) {
       T ex = 0, ox = 0, ey = 0, oy = 0, ez = 0, oz = 0;
@@ -383,6 +427,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
       const T vx0 = fma(dq[0][k], gx0, fma(dq[1][k], gy0, dq[2][k] * gz0));
       const T vy0 = fma(dq[1][k], gx0, fma(dq[3][k], gy0, dq[4][k] * gz0));
       const T vz0 = fma(dq[2][k], gx0, fma(dq[4][k], gy0, dq[5][k] * gz0));
+      if constexpr (DOT) vq = fma(gx0, vx0, fma(gy0, vy0, fma(gz0, vz0, vq)));
       if (k < LQ) {
         // its mirror Q-1-k
         const int m = Q - 1 - k;
@@ -390,6 +435,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
         const T vx1 = fma(dq[0][m], gx1, fma(dq[1][m], gy1, dq[2][m] * gz1));
         const T vy1 = fma(dq[1][m], gx1, fma(dq[3][m], gy1, dq[4][m] * gz1));
         const T vz1 = fma(dq[2][m], gx1, fma(dq[4][m], gy1, dq[5][m] * gz1));
+        if constexpr (DOT) vq = fma(gx1, vx1, fma(gy1, vy1, fma(gz1, vz1, vq)));
         const T fx = vx0 + vx1, gxd = vx0 - vx1, fy = vy0 + vy1, gyd = vy0 - vy1;
         const T fz = vz0 + vz1, gzd = vz0 - vz1;
 #pragma unroll
@@ -410,6 +456,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
         }
       }
     }
+    if constexpr (DOT) vd += (double)vq;
 #pragma unroll
     for (int i = 0; i < HN; ++i) {
       reg0[i * Q * R] = E1[i] + O1[i];
@@ -475,6 +522,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
     E.init(a, eA);
     store_line<P, SCATTER, IDX>(a, E, eA, aA, cA, acc);
   }
+  if constexpr (DOT) workgroup_dot(a.dot_part, vd, e0 / NE);
 }
 
 // ---------------------------------------------------------------------------
@@ -488,6 +536,9 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   constexpr int QQQ = Q * Q * Q;
   using ST = SplitTab<T, P>;
   constexpr int HN = Mir<N>::HE, LN = Mir<N>::H, HQ = Mir<Q>::HE, LQ = Mir<Q>::H;
+
+  constexpr bool DOT = SCATTER == kScatterXRowsDot;
+  double vd = 0.0;  // this thread's share of x . (A x) (DOT only)
 
   const int sC = tid / QQ, rC = tid - sC * QQ;
   const int64_t eC = e0 + sC;
@@ -521,8 +572,14 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
 
   if (actA) {
 #pragma unroll
-    for (int b = 0; b < N; ++b)
-      u[b] = (a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA)) ? T(0) : u[b];
+    for (int b = 0; b < N; ++b) {
+      const bool es = a.constrained && EA.ess(a, EA.dof(aA, b, cA), aA, b, cA);
+      if constexpr (DOT) {
+        const double ub = (es && owns_node<P>(EA, a, aA, b, cA)) ? (double)u[b] : 0.0;
+        vd = fma(ub, ub, vd);
+      }
+      u[b] = es ? T(0) : u[b];
+    }
     T* reg = smem + sA * L + (cA * Q) * R + aA;
     T ue[HN], uo[LN], tb[Q];
     mirror<N>(u, ue, uo);
@@ -559,6 +616,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     const T* MtB = ST::Mt(0);
 #pragma unroll
     for (int i = 0; i < HN; ++i) E[i] = O[i] = 0;
+    T vq = 0;  // sum over this z-line of u . (D u) (DOT only)
 #pragma unroll
     for (int k = 0; k < HQ; ++k) {  // mirror pairs of points (see diff_elements)
       T e = 0, o = 0;
@@ -567,8 +625,10 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
 #pragma unroll
       for (int i = 0; i < LN; ++i) o = fma(MfB[k * LN + i], io[i], o);
       const T v0 = dq[k] * (e + o);
+      if constexpr (DOT) vq = fma(e + o, v0, vq);
       if (k < LQ) {
         const T v1 = dq[Q - 1 - k] * (e - o);
+        if constexpr (DOT) vq = fma(e - o, v1, vq);
         const T f = v0 + v1, g = v0 - v1;
 #pragma unroll
         for (int i = 0; i < HN; ++i) {
@@ -580,6 +640,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
         for (int i = 0; i < HN; ++i) E[i] = fma(PtB[i * HQ + k], v0, E[i]);
       }
     }
+    if constexpr (DOT) vd += (double)vq;
 #pragma unroll
     for (int i = 0; i < HN; ++i) {
       reg0[i * Q * R] = E[i] + O[i];
@@ -612,6 +673,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     E.init(a, eA);
     store_line<P, SCATTER, IDX>(a, E, eA, aA, cA, acc);
   }
+  if constexpr (DOT) workgroup_dot(a.dot_part, vd, e0 / NE);
 }
 
 }  // namespace apply

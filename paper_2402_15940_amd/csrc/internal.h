@@ -162,6 +162,7 @@ struct Op : RefCounted {
   // solver workspace
   DevBuf d_cg;                  // vectors
   DevBuf d_part;                // reduction partials
+  DevBuf d_gpart;               // per-workgroup partials of the element pass (fused CG)
   DevBuf d_state;               // CgState
   DevBuf d_dinv64, d_dinv32;
   bool have_dinv = false;
@@ -211,6 +212,7 @@ struct ApplyArgs {
   int constrained;
   int accumulate;     // atomic mode: y holds a previous result to add to
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
+  double* dot_part;   // if non-null: per workgroup, sum over its elements of x_e . y_e
 };
 
 // Tables of the element kernels for order p (n = p+1 nodes, q = p+2 points):
@@ -244,6 +246,8 @@ hipError_t upload_tables_batched(const double* t64, const float* t32, size_t wor
 // the ordered per-node sum reads consecutive words for consecutive nodes.
 constexpr int kScatterEvector = 2;
 constexpr int kScatterXRows = 3;
+// kScatterXRows plus per-workgroup partials of x . (A x) for CG (a.dot_part).
+constexpr int kScatterXRowsDot = 4;
 
 // Words per element run of the x-interleaved layout (runs may be padded so
 // that they fill whole memory sectors).
@@ -314,6 +318,25 @@ hipError_t launch_cg_init(const T* r, const T* dinv, T* p, int64_t n, double* pa
                           hipStream_t s);
 hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
                                 int maxit, CgState* st, hipStream_t s, double delta2 = 0.0);
+// One CG step fused into the ordered E^T sum of the x-interleaved E-vector
+// yX of A p: x += alpha p, r -= alpha A p, and fixed-partition partials of
+// (r . dinv r, r . r) (*nparts pairs, at most kMaxCgParts).  A p is not stored.
+constexpr int kMaxCgParts = 4096;
+template <typename T, typename TX>
+hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int p, const T* pvec,
+                                  TX* x, T* r, const T* dinv, double* partials, int* nparts,
+                                  const CgState* st, hipStream_t s);
+// alpha from nb partials of p . A p (one 1024-thread workgroup).
+hipError_t launch_cg_alpha_wide(const double* partials, int nb, CgState* st, hipStream_t s);
+// Element pass of A p for CG (deterministic E^T, lattice numbering): writes the
+// x-interleaved E-vector and per-workgroup partials of p_e . (A p)_e to
+// op->d_gpart; returns their count in *nparts.
+template <typename T>
+int apply_elements_dot(Op* op, const T* p, const int* skip, hipStream_t s, int qprec,
+                       int* nparts);
+// Workgroups of the element pass of `kind`, order p, over ne elements.
+int64_t element_blocks(int kind, int p, int64_t ne, bool f32);
+
 // Mixed-precision CG: replace the FP32 recursive residual by rs = (float) r64
 // (r64 = b - A x in FP64), leaving partials of (rs . dinv rs, r64 . r64), and
 // (st non-null) finish the paused iteration's scalars from them.

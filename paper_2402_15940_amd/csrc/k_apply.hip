@@ -64,8 +64,10 @@ hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s) {
 template <int P, typename T, int KIND>
 hipError_t apply_kind(int scatter, int idx, const ApplyArgs<T>& a, hipStream_t s) {
   constexpr int ATO = PAFEM_SCATTER_ATOMIC, EVC = kScatterEvector, XR = kScatterXRows;
+  constexpr int XRD = kScatterXRowsDot;
   constexpr int MAP = PAFEM_INDEX_MAP, LAT = PAFEM_INDEX_LATTICE;
   if (scatter == XR) return launch_one<P, T, KIND, XR, LAT>(a, s);
+  if (scatter == XRD) return launch_one<P, T, KIND, XRD, LAT>(a, s);
   if (scatter == EVC)
     return idx == MAP ? launch_one<P, T, KIND, EVC, MAP>(a, s) : launch_one<P, T, KIND, EVC, LAT>(a, s);
   return idx == MAP ? launch_one<P, T, KIND, ATO, MAP>(a, s) : launch_one<P, T, KIND, ATO, LAT>(a, s);
@@ -84,10 +86,11 @@ template <typename T>
 hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode,
                         const ApplyArgs<T>& a, hipStream_t s) {
   if (q != p + 2) return hipErrorInvalidValue;
-  if (scatter_mode != PAFEM_SCATTER_ATOMIC && scatter_mode != kScatterEvector &&
-      scatter_mode != kScatterXRows)
+  const bool xrows = scatter_mode == kScatterXRows || scatter_mode == kScatterXRowsDot;
+  if (scatter_mode != PAFEM_SCATTER_ATOMIC && scatter_mode != kScatterEvector && !xrows)
     return hipErrorInvalidValue;
-  if (scatter_mode == kScatterXRows && index_mode != PAFEM_INDEX_LATTICE) return hipErrorInvalidValue;
+  if (xrows && index_mode != PAFEM_INDEX_LATTICE) return hipErrorInvalidValue;
+  if (scatter_mode == kScatterXRowsDot && a.dot_part == nullptr) return hipErrorInvalidValue;
   // the stored maps must be on the device before a kernel may read them
   if (index_mode == PAFEM_INDEX_MAP && (a.E == nullptr || a.ess_mask == nullptr))
     return hipErrorInvalidValue;
@@ -118,6 +121,29 @@ hipError_t upload_tables_apply(const double* t64, const float* t32, size_t words
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(apply::c_tab64), t64, words * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(apply::c_tab32), t32, words * sizeof(float));
   return e;
+}
+
+namespace {
+template <typename T, int KIND>
+int64_t blocks_p(int p, int64_t ne) {
+  switch (p) {
+    case 1: return (ne + Cfg<1, 3, T, KIND>::NE - 1) / Cfg<1, 3, T, KIND>::NE;
+    case 2: return (ne + Cfg<2, 4, T, KIND>::NE - 1) / Cfg<2, 4, T, KIND>::NE;
+    case 3: return (ne + Cfg<3, 5, T, KIND>::NE - 1) / Cfg<3, 5, T, KIND>::NE;
+    case 4: return (ne + Cfg<4, 6, T, KIND>::NE - 1) / Cfg<4, 6, T, KIND>::NE;
+    case 5: return (ne + Cfg<5, 7, T, KIND>::NE - 1) / Cfg<5, 7, T, KIND>::NE;
+    case 6: return (ne + Cfg<6, 8, T, KIND>::NE - 1) / Cfg<6, 8, T, KIND>::NE;
+    case 7: return (ne + Cfg<7, 9, T, KIND>::NE - 1) / Cfg<7, 9, T, KIND>::NE;
+    case 8: return (ne + Cfg<8, 10, T, KIND>::NE - 1) / Cfg<8, 10, T, KIND>::NE;
+    default: return 0;
+  }
+}
+}  // namespace
+
+int64_t element_blocks(int kind, int p, int64_t ne, bool f32) {
+  if (kind == PAFEM_DIFFUSION)
+    return f32 ? blocks_p<float, PAFEM_DIFFUSION>(p, ne) : blocks_p<double, PAFEM_DIFFUSION>(p, ne);
+  return f32 ? blocks_p<float, PAFEM_MASS>(p, ne) : blocks_p<double, PAFEM_MASS>(p, ne);
 }
 
 }  // namespace pafem

@@ -135,6 +135,116 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__
   }
 }
 
+// One CG step fused into the ordered E^T sum of the x-interleaved E-vector
+// (the element pass of A p): for every node, with Ap_i the sum formed exactly
+// as in k_gather_xrows (p_i on essential rows),
+//   x_i += alpha p_i,  r_i -= alpha Ap_i,  z_i = dinv_i r_i,
+// and each workgroup writes its partials of (r . z, r . r).  A p never goes
+// through memory.  TX is the type of the solution (FP64 for mixed CG).
+template <typename T, typename TX, int P>
+__global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
+    const T* __restrict__ yX, int nx, int ny, int nz, const T* __restrict__ p, TX* __restrict__ x,
+    T* __restrict__ r, const T* __restrict__ dinv, double* __restrict__ partials,
+    const CgState* __restrict__ st) {
+  constexpr int N = P + 1, R = kXRowsPer;
+  if (st->done) return;
+  const T alpha = (T)st->alpha;
+  const double alpha_x = st->alpha;
+  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1, rows = Ly * Lz;
+  const int I0 = blockIdx.x * kThreads + threadIdx.x;
+  const bool live = I0 < Lx;
+  const int I = live ? I0 : Lx - 1;
+  int ex = I / P, a = I - ex * P;
+  if (ex == nx) {
+    ex = nx - 1;
+    a = P;
+  }
+  const bool xface = a == 0 && ex > 0;
+  constexpr int W = xrows_width(N);
+  const int col = ex * W + a, left = xface ? P - W : 0;
+  double v[2] = {0.0, 0.0}, out[2];
+  for (int row0 = blockIdx.y * R; row0 < rows; row0 += gridDim.y * R) {
+    T vv[R][4], ww[R][4];
+    int cy[R], cz[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = row0 + q < rows ? row0 + q : rows - 1;
+      const int J = row % Ly, K = row / Ly;
+      int ey[2], ly[2], ez[2], lz[2];
+      cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
+      cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
+#pragma unroll
+      for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 2; ++ky) {
+          const int k = 2 * kz + ky;
+          const bool on = kz < cz[q] && ky < cy[q];
+          const T* rp = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
+          vv[q][k] = on ? rp[0] : T(0);
+          ww[q][k] = (on && xface) ? rp[left] : T(0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = row0 + q;
+      if (row >= rows) break;
+      const int J = row % Ly, K = row / Ly;
+      const int64_t i = I + (int64_t)Lx * row;
+      if (!live) continue;
+      T acc = 0;
+      const T pi = p[i];
+      if (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1) {
+        acc = pi;
+      } else {
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky)
+            if (kz < cz[q] && ky < cy[q]) {
+              if (xface) acc += ww[q][2 * kz + ky];
+              acc += vv[q][2 * kz + ky];
+            }
+      }
+      if constexpr (sizeof(TX) == sizeof(T))
+        x[i] += alpha * pi;
+      else
+        x[i] += alpha_x * (TX)pi;
+      const T ri = r[i] - alpha * acc;
+      r[i] = ri;
+      const T zi = dinv[i] * ri;
+      v[0] += (double)ri * (double)zi;
+      v[1] += (double)ri * (double)ri;
+    }
+  }
+  block_sum<2>(v, out);
+  if (threadIdx.x == 0) {
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    partials[2 * b] = out[0];
+    partials[2 * b + 1] = out[1];
+  }
+}
+
+// alpha = r . z / p . Ap from many partials of p . Ap (one workgroup of 1024
+// threads, fixed order).
+constexpr int kWideThreads = 1024;
+__global__ __launch_bounds__(kWideThreads) void k_cg_alpha_wide(const double* __restrict__ partials,
+                                                                 int nb, CgState* st) {
+  if (st->done) return;
+  __shared__ double sh[kWideThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kWideThreads) acc += partials[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kWideThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->pAp = sh[0];
+    st->alpha = st->rz / sh[0];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_set_ess(const int32_t* __restrict__ ess, int64_t n,
                                                       const T* __restrict__ x, T value,
@@ -593,6 +703,55 @@ hipError_t launch_axpy_from_f32(double* x, const double* norm2, const float* d32
 hipError_t launch_recip(const double* d, double* dinv64, float* dinv32, int64_t n,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_recip, dim3(grid_for(n)), dim3(kThreads), 0, s, d, dinv64, dinv32, n);
+  return hipGetLastError();
+}
+
+template <typename T, typename TX, int P>
+hipError_t gather_xrows_cg_p(const T* yX, int nx, int ny, int nz, const T* p, TX* x, T* r,
+                             const T* dinv, double* partials, int* nparts, const CgState* st,
+                             hipStream_t s) {
+  const int64_t Lx = (int64_t)nx * P + 1, rows = ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
+  const int64_t groups = (rows + kXRowsPer - 1) / kXRowsPer;
+  const int64_t gx = (Lx + kThreads - 1) / kThreads;
+  if (gx > kMaxCgParts) return hipErrorInvalidValue;
+  int64_t gy = groups;
+  if (gx * gy > kMaxCgParts) gy = kMaxCgParts / gx;
+  *nparts = (int)(gx * gy);
+  hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P>), dim3((unsigned)gx, (unsigned)gy),
+                     dim3(kThreads), 0, s, yX, nx, ny, nz, p, x, r, dinv, partials, st);
+  return hipGetLastError();
+}
+
+template <typename T, typename TX>
+hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int pdeg, const T* p,
+                                  TX* x, T* r, const T* dinv, double* partials, int* nparts,
+                                  const CgState* st, hipStream_t s) {
+  if (nx <= 0 || ny <= 0 || nz <= 0) return hipErrorInvalidValue;
+  switch (pdeg) {
+#define PAFEM_CASE(PP) \
+  case PP:             \
+    return gather_xrows_cg_p<T, TX, PP>(yX, nx, ny, nz, p, x, r, dinv, partials, nparts, st, s);
+    PAFEM_CASE(1) PAFEM_CASE(2) PAFEM_CASE(3) PAFEM_CASE(4)
+    PAFEM_CASE(5) PAFEM_CASE(6) PAFEM_CASE(7) PAFEM_CASE(8)
+#undef PAFEM_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_gather_xrows_cg<double, double>(const double*, int, int, int, int,
+                                                           const double*, double*, double*,
+                                                           const double*, double*, int*,
+                                                           const CgState*, hipStream_t);
+template hipError_t launch_gather_xrows_cg<float, float>(const float*, int, int, int, int,
+                                                         const float*, float*, float*,
+                                                         const float*, double*, int*,
+                                                         const CgState*, hipStream_t);
+template hipError_t launch_gather_xrows_cg<float, double>(const float*, int, int, int, int,
+                                                          const float*, double*, float*,
+                                                          const float*, double*, int*,
+                                                          const CgState*, hipStream_t);
+
+hipError_t launch_cg_alpha_wide(const double* partials, int nb, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha_wide, dim3(1), dim3(kWideThreads), 0, s, partials, nb, st);
   return hipGetLastError();
 }
 

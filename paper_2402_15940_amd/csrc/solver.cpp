@@ -2,9 +2,12 @@
 // operator: plain FP64, FP64 defect correction around an FP32 inner PCG, and
 // one mixed-precision PCG with FP64 residual replacement.
 //
-// All CG scalars live in a device-resident CgState; one iteration is six
-// kernels (apply, p.Ap partial dot, alpha, update + (r.z, r.r) partials,
-// beta, direction update) with no host round trip.  The host reads the state
+// All CG scalars live in a device-resident CgState; one iteration is a fixed
+// sequence of kernels with no host round trip: on the lattice numbering with
+// the deterministic E^T, five (element pass + p.Ap partials, alpha, E^T sum +
+// x and r updates + (r.z, r.r) partials, beta, direction update), otherwise
+// seven (apply as element pass and E^T, p.Ap partial dot, alpha, update +
+// partials, beta, direction update).  The host reads the state
 // every `check_every` iterations; kernels of iterations enqueued after
 // convergence see state.done and return at once.
 #include <chrono>
@@ -24,6 +27,41 @@ struct CgResult {
   bool converged = false;
 };
 
+// Reduction partials: pairs for the vector kernels (reduce_blocks) and for the
+// fused CG step (at most kMaxCgParts), then 8 scalar slots.  Sized once for
+// both, so that no caller's pointers into it go stale.
+int partial_pairs(int64_t n) {
+  const int nb = reduce_blocks(n);
+  return nb > kMaxCgParts ? nb : kMaxCgParts;
+}
+int ensure_partials(Op* op, int64_t n) {
+  return op->d_part.ensure(((size_t)partial_pairs(n) * 2 + 8) * sizeof(double));
+}
+
+// The deterministic E^T on the lattice numbering lets one CG step run as
+// three passes over memory instead of five: the element pass of A p also
+// forms p . A p per workgroup, and the ordered E^T sum applies the updates of
+// x and r and forms (r . z, r . r) without storing A p.
+bool fused_cg(const Op* op) {
+  return op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC && op->index_mode == PAFEM_INDEX_LATTICE;
+}
+
+// alpha, x += alpha p, r -= alpha A p, beta (the direction update follows).
+// part holds at least kMaxCgParts pairs.
+template <typename TX, typename T>
+int cg_step_fused(Op* op, TX* x, T* r, const T* p, const T* dinv, double* part, CgState* st,
+                  hipStream_t s, int qprec) {
+  Space* sp = op->space;
+  int ne_parts = 0, g_parts = 0;
+  PAFEM_TRY(apply_elements_dot<T>(op, p, &st->done, s, qprec, &ne_parts));
+  PAFEM_TRY_HIP(launch_cg_alpha_wide(op->d_gpart.as<double>(), ne_parts, st, s));
+  PAFEM_TRY_HIP((launch_gather_xrows_cg<T, TX>(op->d_evec.as<T>(), sp->mesh->nx, sp->mesh->ny,
+                                               sp->mesh->nz, sp->p, p, x, r, dinv, part,
+                                               &g_parts, st, s)));
+  PAFEM_TRY_HIP(launch_cg_beta(part, g_parts, st, s));
+  return PAFEM_OK;
+}
+
 // Solve A x = rhs for the constrained operator in precision T.  On entry x is
 // the initial guess unless x0_zero.  r, p, Ap are work vectors of length n.
 template <typename T>
@@ -33,10 +71,10 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
   Space* sp = op->space;
   const int64_t n = sp->ndofs;
   const int nb = reduce_blocks(n);
-  PAFEM_TRY(op->d_part.ensure((size_t)nb * 2 * sizeof(double) + 8 * sizeof(double)));
+  PAFEM_TRY(ensure_partials(op, n));
   PAFEM_TRY(op->d_state.ensure(sizeof(CgState)));
   double* part = op->d_part.as<double>();
-  double* bbdev = part + 2 * nb;
+  double* bbdev = part + 2 * partial_pairs(n);
   CgState* st = op->d_state.as<CgState>();
 
   // b.b for the stopping test
@@ -68,11 +106,15 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
   CgState hs{};
   for (;;) {
     for (int k = 0; k < check_every; ++k) {
-      PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
-      PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
-      PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
-      PAFEM_TRY_HIP((launch_cg_update<T, T>(x, r, p, Ap, dinv, n, part, nb, st, s)));
-      PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+      if (fused_cg(op)) {
+        PAFEM_TRY((cg_step_fused<T, T>(op, x, r, p, dinv, part, st, s, qprec)));
+      } else {
+        PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
+        PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
+        PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
+        PAFEM_TRY_HIP((launch_cg_update<T, T>(x, r, p, Ap, dinv, n, part, nb, st, s)));
+        PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+      }
       PAFEM_TRY_HIP(launch_cg_pupdate<T>(p, r, dinv, n, st, s));
     }
     PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -98,10 +140,10 @@ int run_mixed(Op* op, const double* b, double* x, double* r64, double* Ax, float
   Space* sp = op->space;
   const int64_t n = sp->ndofs;
   const int nb = reduce_blocks(n);
-  PAFEM_TRY(op->d_part.ensure((size_t)nb * 2 * sizeof(double) + 8 * sizeof(double)));
+  PAFEM_TRY(ensure_partials(op, n));
   PAFEM_TRY(op->d_state.ensure(sizeof(CgState)));
   double* part = op->d_part.as<double>();
-  double* bbdev = part + 2 * nb;
+  double* bbdev = part + 2 * partial_pairs(n);
   CgState* st = op->d_state.as<CgState>();
 
   PAFEM_TRY_HIP(launch_dot_partial<double>(b, b, n, part, nb, nullptr, s));
@@ -124,11 +166,15 @@ int run_mixed(Op* op, const double* b, double* x, double* r64, double* Ax, float
   replacements = 0;
   for (;;) {
     for (int k = 0; k < check_every; ++k) {
-      PAFEM_TRY(apply_impl<float>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
-      PAFEM_TRY_HIP(launch_dot_partial<float>(p, Ap, n, part, nb, done, s));
-      PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
-      PAFEM_TRY_HIP((launch_cg_update<double, float>(x, rs, p, Ap, dinv, n, part, nb, st, s)));
-      PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+      if (fused_cg(op)) {
+        PAFEM_TRY((cg_step_fused<double, float>(op, x, rs, p, dinv, part, st, s, qprec)));
+      } else {
+        PAFEM_TRY(apply_impl<float>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
+        PAFEM_TRY_HIP(launch_dot_partial<float>(p, Ap, n, part, nb, done, s));
+        PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
+        PAFEM_TRY_HIP((launch_cg_update<double, float>(x, rs, p, Ap, dinv, n, part, nb, st, s)));
+        PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+      }
       PAFEM_TRY_HIP(launch_cg_pupdate<float>(p, rs, dinv, n, st, s));
     }
     PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -268,9 +314,9 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     float* p32 = r32 + n;
     float* Ap32 = p32 + n;
     const int nb = reduce_blocks(n);
-    PAFEM_TRY(op->d_part.ensure((size_t)nb * 2 * sizeof(double) + 8 * sizeof(double)));
+    PAFEM_TRY(ensure_partials(op, n));
     double* part = op->d_part.as<double>();
-    double* rr_dev = part + 2 * nb + 2;  // ||r||^2 of the current outer residual
+    double* rr_dev = part + 2 * partial_pairs(n) + 2;  // ||r||^2 of the current outer residual
     // bb
     PAFEM_TRY_HIP(launch_dot_partial<double>(b, b, n, part, nb, nullptr, s));
     PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, rr_dev, s));

@@ -539,3 +539,32 @@ def test_mixed_solve_limits_and_nonzero_guess(pf, ctx):
     x64, _ = op.solve(b, mode=pf.SOLVE_PLAIN_FP64, rtol=1e-12)
     assert st2["true_rel_res"] <= 1e-10
     assert ((x2 - x64).norm() / x64.norm()).item() < 1e-8
+
+
+@pytest.mark.parametrize("p", [2, 3, 6])
+def test_fused_cg_step_matches_separate_kernels(pf, ctx, p):
+    """On the lattice numbering one CG step runs fused (p . A p formed in the
+    element pass, the x and r updates in the ordered E^T sum); on the stored
+    map it runs as separate apply, dot and update kernels.  Both are the same
+    Jacobi-PCG: same iteration counts (up to one), same solution.  The initial
+    guess is nonzero on the boundary, so the essential rows of the direction
+    are nonzero and their p_i^2 share of p . A p is exercised."""
+    n = 3
+    v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
+    op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, v), p), pf.DIFFUSION)
+    op.set_coefficient_sinx(0.5)
+    op.assemble(pf.FP64 | pf.FP32)
+    b = op.rhs()
+    x0 = torch.from_numpy(inputs.random_vector(op.space.ndofs, 5)).cuda()
+    for mode, inner in ((pf.SOLVE_PLAIN_FP64, 1e-3), (pf.SOLVE_IR_FP32, 1e-3),
+                        (pf.SOLVE_MIXED_FP32, 0.1)):
+        out = {}
+        for im in (pf.INDEX_LATTICE, pf.INDEX_MAP):
+            op.set_restriction_mode(im)
+            x, st = op.solve(b, x0.clone(), mode=mode, rtol=1e-10, inner_rtol=inner)
+            assert st["true_rel_res"] <= 1.5e-10, (mode, im, st)
+            out[im] = (x, st["iterations"])
+        (xl, il), (xm, im_) = out[pf.INDEX_LATTICE], out[pf.INDEX_MAP]
+        assert abs(il - im_) <= 1, (mode, il, im_)
+        assert ((xl - xm).norm() / xm.norm()).item() < 1e-9, mode
+    op.set_restriction_mode(pf.INDEX_LATTICE)
