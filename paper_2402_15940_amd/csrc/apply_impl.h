@@ -49,6 +49,11 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 #endif
 constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
 constexpr int kWavesDiff64[] = {PAFEM_WAVES_DIFF_F64};
+// the same for the element pass that also forms the CG dot product
+#ifndef PAFEM_WAVES_DIFF_F64_DOT
+#define PAFEM_WAVES_DIFF_F64_DOT 1, 1, 1, 1, 3, 3, 1, 1, 1
+#endif
+constexpr int kWavesDiff64Dot[] = {PAFEM_WAVES_DIFF_F64_DOT};
 
 // The 1D tables B[q][n], G[q][n] (q = p+2 Gauss-Legendre points, n = p+1 GLL
 // nodes) depend on p alone, so every element kernel reads them from constant
@@ -137,6 +142,8 @@ struct Cfg {
   // waves per SIMD the register allocation must allow (occupancy floor)
   static constexpr int MIN_WAVES =
       (KIND == PAFEM_DIFFUSION && sizeof(T) == 8) ? kWavesDiff64[P] : 1;
+  static constexpr int MIN_WAVES_DOT =
+      (KIND == PAFEM_DIFFUSION && sizeof(T) == 8) ? kWavesDiff64Dot[P] : 1;
   static_assert(NE * L * (int)sizeof(T) <= 64 * 1024, "LDS budget");
 };
 

@@ -14,7 +14,9 @@ using apply::xcd_block;
 
 template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
-                             (Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES)) void k_apply_diff(
+                             (SCATTER == kScatterXRowsDot
+                                  ? Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES_DOT
+                                  : Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES)) void k_apply_diff(
     ApplyArgs<T> a) {
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
   __shared__ T smem[C::NE * C::L];
