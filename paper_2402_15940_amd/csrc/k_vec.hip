@@ -225,23 +225,30 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
 }
 
 // alpha = r . z / p . Ap from many partials of p . Ap (one workgroup of 1024
-// threads, fixed order).
+// threads, fixed order: four running sums per thread, wavefront shuffles, one
+// pass over the wavefront sums).
 constexpr int kWideThreads = 1024;
 __global__ __launch_bounds__(kWideThreads) void k_cg_alpha_wide(const double* __restrict__ partials,
                                                                  int nb, CgState* st) {
   if (st->done) return;
-  __shared__ double sh[kWideThreads];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kWideThreads) acc += partials[i];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = kWideThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+  __shared__ double sh[kWideThreads / 64];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int i = threadIdx.x;
+  for (; i + 3 * kWideThreads < nb; i += 4 * kWideThreads) {
+    a0 += partials[i];
+    a1 += partials[i + kWideThreads];
+    a2 += partials[i + 2 * kWideThreads];
+    a3 += partials[i + 3 * kWideThreads];
   }
+  for (; i < nb; i += kWideThreads) a0 += partials[i];
+  const double w = vec::wave_sum((a0 + a1) + (a2 + a3));
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = w;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    st->pAp = sh[0];
-    st->alpha = st->rz / sh[0];
+    double t = 0.0;
+    for (int k = 0; k < kWideThreads / 64; ++k) t += sh[k];
+    st->pAp = t;
+    st->alpha = st->rz / t;
   }
 }
 

@@ -55,23 +55,35 @@ __device__ __forceinline__ int lattice_cands(int I, int n, int p, int (&e)[2], i
   return 1;
 }
 
-// Sum `ncols` interleaved columns of partials[nb][ncols] in fixed order.
+// Sum `ncols` (at most 4) interleaved columns of partials[nb][ncols] in a
+// fixed order; a workgroup of kThreads threads calls it, results in thread 0.
+// Each thread keeps four independent running sums over its fixed strided
+// subset (so several loads are in flight), then wavefront shuffles and one
+// pass over the per-wavefront sums combine them.
 __device__ __forceinline__ void final_sums(const double* partials, int nb, int ncols,
                                            double* out) {
-  __shared__ double s[4][kThreads];
+  __shared__ double s[4][kThreads / kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   for (int c = 0; c < ncols; ++c) {
-    double acc = 0;
-    for (int i = threadIdx.x; i < nb; i += kThreads) acc += partials[i * ncols + c];
-    s[c][threadIdx.x] = acc;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int i = threadIdx.x;
+    for (; i + 3 * kThreads < nb; i += 4 * kThreads) {
+      a0 += partials[(int64_t)i * ncols + c];
+      a1 += partials[(int64_t)(i + kThreads) * ncols + c];
+      a2 += partials[(int64_t)(i + 2 * kThreads) * ncols + c];
+      a3 += partials[(int64_t)(i + 3 * kThreads) * ncols + c];
+    }
+    for (; i < nb; i += kThreads) a0 += partials[(int64_t)i * ncols + c];
+    const double w = wave_sum((a0 + a1) + (a2 + a3));
+    if (lane == 0) s[c][wid] = w;
   }
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int c = 0; c < ncols; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
-    __syncthreads();
-  }
   if (threadIdx.x == 0)
-    for (int c = 0; c < ncols; ++c) out[c] = s[c][0];
+    for (int c = 0; c < ncols; ++c) {
+      double acc = 0;
+      for (int k = 0; k < kThreads / kWave; ++k) acc += s[c][k];
+      out[c] = acc;
+    }
 }
 
 // E^T at lattice node (I, J, K): the sum of its element contributions in the
