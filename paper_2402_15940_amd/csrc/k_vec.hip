@@ -59,117 +59,118 @@ __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict
                                       row % Ly, row / Ly);
 }
 
-// E^T from the x-interleaved E-vector: one workgroup per group of kXRowsPer
-// consecutive lattice rows (J, K), one thread per node I of those rows.  The
-// rows' (y, z) element candidates and the start of each candidate's run of
-// words are workgroup-uniform; node I = ex p + a reads word ex (p+1) + a of
-// every run (neighbouring threads: neighbouring words) and, on an x face
-// (a = 0, ex > 0), also the word before it (element ex-1, local p).  All loads
-// of the group are issued before the first sum, for memory-level parallelism.
-// Each node's sum runs in ascending (element, local node) order: for every
-// (z, y) candidate in ascending order, element ex-1 before element ex.
-constexpr int kXRowsPer = 4;
+// E^T from the x-interleaved E-vector, one thread per kXRowsNodes nodes:
+// workgroup b takes the kXRowsNodes * kThreads consecutive lattice nodes from
+// b kXRowsNodes kThreads on (lane t: nodes base + q kThreads + t), so every
+// lane is busy and a wavefront may span the end of a lattice row.  Node
+// I = ex p + a of row (J, K) reads word ex w + a of each (y, z) candidate's
+// run (neighbouring lanes: neighbouring words) and, on an x face (a = 0,
+// ex > 0), also the word of element ex-1's local p.  All loads of a thread
+// are issued before its first sum.  Each node's sum runs in ascending
+// (element, local node) order: for every (z, y) candidate in ascending order,
+// element ex-1 before element ex (the order of the stored map's CSR sum, so
+// the lattice and map forms agree bitwise).
+constexpr int kXRowsNodes = 2;
 
 template <typename T, int P>
-__global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__ yX, int nx,
-                                                           int ny, int nz, int constrained,
-                                                           int accumulate, const T* __restrict__ x,
-                                                           T* __restrict__ y, const int* skip) {
-  constexpr int N = P + 1, R = kXRowsPer;
+__global__ __launch_bounds__(kThreads) void k_gather_xrows(
+    const T* __restrict__ yX, int nx, int ny, int nz, int constrained, int accumulate,
+    const T* __restrict__ x, T* __restrict__ y, const int* skip) {
+  constexpr int N = P + 1, R = kXRowsNodes, W = xrows_width(N);
   if (skip != nullptr && *skip) return;
-  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1, rows = Ly * Lz;
-  const int I = blockIdx.x * kThreads + threadIdx.x;
-  if (I >= Lx) return;
-  int ex = I / P, a = I - ex * P;
-  if (ex == nx) {  // the row's last node
-    ex = nx - 1;
-    a = P;
-  }
-  const bool xface = a == 0 && ex > 0;
-  // word of node I in a run; left: offset of element ex-1's local p from it on
-  // x faces (0 elsewhere, so that the address stays in bounds)
-  constexpr int W = xrows_width(N);
-  const int col = ex * W + a, left = xface ? P - W : 0;
-  for (int row0 = blockIdx.y * R; row0 < rows; row0 += gridDim.y * R) {
-    T v[R][4], w[R][4];
-    int cy[R], cz[R];
+  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1;
+  const int64_t n = (int64_t)Lx * Ly * Lz;
+  const int64_t base = (int64_t)blockIdx.x * (kThreads * R) + threadIdx.x;
+  T v[R][4], w[R][4];
+  int cy[R], cz[R], Iq[R], Jq[R], Kq[R];
+  bool xf[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int row = row0 + q < rows ? row0 + q : rows - 1;
-      const int J = row % Ly, K = row / Ly;
-      int ey[2], ly[2], ez[2], lz[2];
-      cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
-      cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
+  for (int q = 0; q < R; ++q) {
+    const int64_t iq = base + q * kThreads;
+    const int i = (int)(iq < n ? iq : n - 1);
+    const int row = i / Lx, I = i - row * Lx, J = row % Ly, K = row / Ly;
+    int ex = I / P, a = I - ex * P;
+    if (ex == nx) {  // the row's last node
+      ex = nx - 1;
+      a = P;
+    }
+    const bool xface = a == 0 && ex > 0;
+    const int col = ex * W + a, left = xface ? P - W : 0;
+    int ey[2], ly[2], ez[2], lz[2];
+    cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
+    cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < 2; ++ky) {
+        const int k = 2 * kz + ky;
+        const bool on = kz < cz[q] && ky < cy[q];
+        const T* r = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
+        v[q][k] = on ? r[0] : T(0);
+        w[q][k] = (on && xface) ? r[left] : T(0);
+      }
+    Iq[q] = I;
+    Jq[q] = J;
+    Kq[q] = K;
+    xf[q] = xface;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int64_t i = base + q * kThreads;
+    if (i >= n) break;
+    const int I = Iq[q], J = Jq[q], K = Kq[q];
+    T acc = 0;
+    if (constrained && (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1)) {
+      acc = x ? x[i] : T(0);
+    } else {
 #pragma unroll
       for (int kz = 0; kz < 2; ++kz)
 #pragma unroll
-        for (int ky = 0; ky < 2; ++ky) {
-          const int k = 2 * kz + ky;
-          const bool on = kz < cz[q] && ky < cy[q];
-          const T* r = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
-          v[q][k] = on ? r[0] : T(0);
-          w[q][k] = (on && xface) ? r[left] : T(0);
-        }
+        for (int ky = 0; ky < 2; ++ky)
+          if (kz < cz[q] && ky < cy[q]) {
+            if (xf[q]) acc += w[q][2 * kz + ky];
+            acc += v[q][2 * kz + ky];
+          }
     }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int row = row0 + q;
-      if (row >= rows) break;
-      const int J = row % Ly, K = row / Ly;
-      const int64_t i = I + (int64_t)Lx * row;
-      T acc = 0;
-      if (constrained && (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1)) {
-        acc = x ? x[i] : T(0);
-      } else {
-#pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-          for (int ky = 0; ky < 2; ++ky)
-            if (kz < cz[q] && ky < cy[q]) {
-              if (xface) acc += w[q][2 * kz + ky];
-              acc += v[q][2 * kz + ky];
-            }
-      }
-      y[i] = accumulate ? y[i] + acc : acc;
-    }
+    y[i] = accumulate ? y[i] + acc : acc;
   }
 }
 
 // One CG step fused into the ordered E^T sum of the x-interleaved E-vector
-// (the element pass of A p): for every node, with Ap_i the sum formed exactly
-// as in k_gather_xrows (p_i on essential rows),
-//   x_i += alpha p_i,  r_i -= alpha Ap_i,  z_i = dinv_i r_i,
-// and each workgroup writes its partials of (r . z, r . r).  A p never goes
-// through memory.  TX is the type of the solution (FP64 for mixed CG).
+// of A p (the node mapping and summation order of k_gather_xrows, p_i on
+// essential rows): x_i += alpha p_i, r_i -= alpha (A p)_i, z_i = dinv_i r_i,
+// and each workgroup's partials of (r . z, r . r).  A p never goes through
+// memory.  A capped grid strides over the chunks of nodes; TX is the type of
+// the solution (FP64 for mixed CG).
 template <typename T, typename TX, int P>
 __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
     const T* __restrict__ yX, int nx, int ny, int nz, const T* __restrict__ p, TX* __restrict__ x,
     T* __restrict__ r, const T* __restrict__ dinv, double* __restrict__ partials,
     const CgState* __restrict__ st) {
-  constexpr int N = P + 1, R = kXRowsPer;
+  constexpr int N = P + 1, R = kXRowsNodes, W = xrows_width(N);
   if (st->done) return;
   const T alpha = (T)st->alpha;
   const double alpha_x = st->alpha;
-  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1, rows = Ly * Lz;
-  const int I0 = blockIdx.x * kThreads + threadIdx.x;
-  const bool live = I0 < Lx;
-  const int I = live ? I0 : Lx - 1;
-  int ex = I / P, a = I - ex * P;
-  if (ex == nx) {
-    ex = nx - 1;
-    a = P;
-  }
-  const bool xface = a == 0 && ex > 0;
-  constexpr int W = xrows_width(N);
-  const int col = ex * W + a, left = xface ? P - W : 0;
-  double v[2] = {0.0, 0.0}, out[2];
-  for (int row0 = blockIdx.y * R; row0 < rows; row0 += gridDim.y * R) {
-    T vv[R][4], ww[R][4];
-    int cy[R], cz[R];
+  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1;
+  const int64_t n = (int64_t)Lx * Ly * Lz;
+  double v2[2] = {0.0, 0.0}, out[2];
+  for (int64_t base = (int64_t)blockIdx.x * (kThreads * R) + threadIdx.x; base - threadIdx.x < n;
+       base += (int64_t)gridDim.x * (kThreads * R)) {
+    T v[R][4], w[R][4];
+    int cy[R], cz[R], Iq[R], Jq[R], Kq[R];
+    bool xf[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int row = row0 + q < rows ? row0 + q : rows - 1;
-      const int J = row % Ly, K = row / Ly;
+      const int64_t iq = base + q * kThreads;
+      const int i = (int)(iq < n ? iq : n - 1);
+      const int row = i / Lx, I = i - row * Lx, J = row % Ly, K = row / Ly;
+      int ex = I / P, a = I - ex * P;
+      if (ex == nx) {
+        ex = nx - 1;
+        a = P;
+      }
+      const bool xface = a == 0 && ex > 0;
+      const int col = ex * W + a, left = xface ? P - W : 0;
       int ey[2], ly[2], ez[2], lz[2];
       cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
       cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
@@ -180,19 +181,21 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
           const int k = 2 * kz + ky;
           const bool on = kz < cz[q] && ky < cy[q];
           const T* rp = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
-          vv[q][k] = on ? rp[0] : T(0);
-          ww[q][k] = (on && xface) ? rp[left] : T(0);
+          v[q][k] = on ? rp[0] : T(0);
+          w[q][k] = (on && xface) ? rp[left] : T(0);
         }
+      Iq[q] = I;
+      Jq[q] = J;
+      Kq[q] = K;
+      xf[q] = xface;
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int row = row0 + q;
-      if (row >= rows) break;
-      const int J = row % Ly, K = row / Ly;
-      const int64_t i = I + (int64_t)Lx * row;
-      if (!live) continue;
-      T acc = 0;
+      const int64_t i = base + q * kThreads;
+      if (i >= n) break;
+      const int I = Iq[q], J = Jq[q], K = Kq[q];
       const T pi = p[i];
+      T acc = 0;
       if (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1) {
         acc = pi;
       } else {
@@ -201,8 +204,8 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
 #pragma unroll
           for (int ky = 0; ky < 2; ++ky)
             if (kz < cz[q] && ky < cy[q]) {
-              if (xface) acc += ww[q][2 * kz + ky];
-              acc += vv[q][2 * kz + ky];
+              if (xf[q]) acc += w[q][2 * kz + ky];
+              acc += v[q][2 * kz + ky];
             }
       }
       if constexpr (sizeof(TX) == sizeof(T))
@@ -212,15 +215,14 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
       const T ri = r[i] - alpha * acc;
       r[i] = ri;
       const T zi = dinv[i] * ri;
-      v[0] += (double)ri * (double)zi;
-      v[1] += (double)ri * (double)ri;
+      v2[0] += (double)ri * (double)zi;
+      v2[1] += (double)ri * (double)ri;
     }
   }
-  block_sum<2>(v, out);
+  block_sum<2>(v2, out);
   if (threadIdx.x == 0) {
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
-    partials[2 * b] = out[0];
-    partials[2 * b + 1] = out[1];
+    partials[2 * blockIdx.x] = out[0];
+    partials[2 * blockIdx.x + 1] = out[1];
   }
 }
 
@@ -548,12 +550,10 @@ hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int
 template <typename T, int P>
 hipError_t gather_xrows_p(const T* yX, int nx, int ny, int nz, int constrained, int accumulate,
                           const T* x, T* y, const int* skip, hipStream_t s) {
-  const int64_t Lx = (int64_t)nx * P + 1, rows = ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
-  const int64_t groups = (rows + kXRowsPer - 1) / kXRowsPer;
-  const dim3 grid((unsigned)((Lx + kThreads - 1) / kThreads),
-                  (unsigned)(groups < 65535 ? groups : 65535));
-  hipLaunchKernelGGL((k_gather_xrows<T, P>), grid, dim3(kThreads), 0, s, yX, nx, ny, nz,
-                     constrained, accumulate, x, y, skip);
+  const int64_t nodes = ((int64_t)nx * P + 1) * ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
+  const int64_t per = (int64_t)kThreads * kXRowsNodes;
+  hipLaunchKernelGGL((k_gather_xrows<T, P>), dim3((unsigned)((nodes + per - 1) / per)),
+                     dim3(kThreads), 0, s, yX, nx, ny, nz, constrained, accumulate, x, y, skip);
   return hipGetLastError();
 }
 
@@ -717,15 +717,13 @@ template <typename T, typename TX, int P>
 hipError_t gather_xrows_cg_p(const T* yX, int nx, int ny, int nz, const T* p, TX* x, T* r,
                              const T* dinv, double* partials, int* nparts, const CgState* st,
                              hipStream_t s) {
-  const int64_t Lx = (int64_t)nx * P + 1, rows = ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
-  const int64_t groups = (rows + kXRowsPer - 1) / kXRowsPer;
-  const int64_t gx = (Lx + kThreads - 1) / kThreads;
-  if (gx > kMaxCgParts) return hipErrorInvalidValue;
-  int64_t gy = groups;
-  if (gx * gy > kMaxCgParts) gy = kMaxCgParts / gx;
-  *nparts = (int)(gx * gy);
-  hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P>), dim3((unsigned)gx, (unsigned)gy),
-                     dim3(kThreads), 0, s, yX, nx, ny, nz, p, x, r, dinv, partials, st);
+  const int64_t nodes = ((int64_t)nx * P + 1) * ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
+  const int64_t per = (int64_t)kThreads * kXRowsNodes;
+  int64_t nblk = (nodes + per - 1) / per;
+  if (nblk > kMaxCgParts) nblk = kMaxCgParts;  // the workgroups stride over the rest
+  *nparts = (int)nblk;
+  hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
+                     yX, nx, ny, nz, p, x, r, dinv, partials, st);
   return hipGetLastError();
 }
 
