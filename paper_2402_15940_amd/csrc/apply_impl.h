@@ -48,6 +48,12 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 #define PAFEM_WAVES_DIFF_F64 1, 1, 1, 1, 4, 1, 1, 1, 1
 #endif
 constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
+// quadrature-data loads by p: 1 = non-temporal (streamed past the caches),
+// 0 = ordinary
+#ifndef PAFEM_NT_QD_BY_P
+#define PAFEM_NT_QD_BY_P 1, 1, 1, 0, 0, 0, 1, 0, 1
+#endif
+constexpr int kNtQd[] = {PAFEM_NT_QD_BY_P};
 constexpr int kWavesDiff64[] = {PAFEM_WAVES_DIFF_F64};
 // the same for the element pass that also forms the CG dot product
 #ifndef PAFEM_WAVES_DIFF_F64_DOT
@@ -321,14 +327,18 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
         for (int k = 0; k < 6; ++k)
           dq[k][qz] = (T)bf16_to_float(__builtin_nontemporal_load(qd + k * QQQ + qz * QQ));
     } else {
-      // issued in the order stage C consumes them (qz outer), so it can start
-      // on the first points while the rest are still arriving
+      // component-major issue order (each component's z-line is one run of
+      // addresses); ordinary or non-temporal loads by p, as measured
       const T* qd = a.qd + off;
 #pragma unroll
-      for (int qz = 0; qz < Q; ++qz) {
+      for (int k = 0; k < 6; ++k) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
-        __builtin_amdgcn_sched_barrier(0);
+        for (int qz = 0; qz < Q; ++qz) {
+          if constexpr (kNtQd[P] != 0)
+            dq[k][qz] = __builtin_nontemporal_load(qd + k * QQQ + qz * QQ);
+          else
+            dq[k][qz] = qd[k * QQQ + qz * QQ];
+        }
       }
     }
   }
