@@ -731,7 +731,10 @@ template <typename T, typename TX>
 hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int pdeg, const T* p,
                                   TX* x, T* r, const T* dinv, double* partials, int* nparts,
                                   const CgState* st, hipStream_t s) {
-  if (nx <= 0 || ny <= 0 || nz <= 0) return hipErrorInvalidValue;
+  if (nx <= 0 || ny <= 0 || nz <= 0 || pdeg < 1) return hipErrorInvalidValue;
+  const int64_t nodes = ((int64_t)nx * pdeg + 1) * ((int64_t)ny * pdeg + 1) *
+                        ((int64_t)nz * pdeg + 1);
+  if (nodes > 0x7fffffff) return hipErrorInvalidValue;  // 32-bit node indices
   switch (pdeg) {
 #define PAFEM_CASE(PP) \
   case PP:             \
