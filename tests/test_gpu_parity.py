@@ -568,3 +568,27 @@ def test_fused_cg_step_matches_separate_kernels(pf, ctx, p):
         assert abs(il - im_) <= 1, (mode, il, im_)
         assert ((xl - xm).norm() / xm.norm()).item() < 1e-9, mode
     op.set_restriction_mode(pf.INDEX_LATTICE)
+
+
+def test_fused_cg_full_size_matches_separate_kernels(pf, ctx):
+    """At the full 7.9M-dof p=6 size, 30 iterations of the fused CG (lattice
+    numbering) and of the separate-kernel CG (stored maps) from the same start
+    agree: the two differ only in the order of the p.Ap and (r.z, r.r) sums."""
+    n, p = 33, 6
+    v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
+    op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, v), p), pf.DIFFUSION)
+    op.set_coefficient_sinx(0.5)
+    op.assemble(pf.FP64 | pf.FP32)
+    b = op.rhs()
+    for mode, tol in ((pf.SOLVE_PLAIN_FP64, 1e-11), (pf.SOLVE_MIXED_FP32, 1e-5)):
+        out = {}
+        for im in (pf.INDEX_LATTICE, pf.INDEX_MAP):
+            op.set_restriction_mode(im)
+            x, st = op.solve(b, mode=mode, rtol=1e-30, inner_rtol=0.1, maxit=30, check_every=10,
+                             raise_on_nonconvergence=False)
+            assert st["iterations"] == 30
+            out[im] = (x, st["rel_res"])
+        (xl, rl), (xm, rm) = out[pf.INDEX_LATTICE], out[pf.INDEX_MAP]
+        assert ((xl - xm).norm() / xm.norm()).item() < tol, mode
+        assert abs(rl - rm) <= tol * rm, (mode, rl, rm)
+    op.set_restriction_mode(pf.INDEX_LATTICE)
