@@ -221,6 +221,75 @@ def test_exact_energies_linear_on_perturbed_mesh(p):
     assert abs(u @ (M @ u) - exact_m) < 1e-13
 
 
+def _cube_moment(i, j, k):
+    """Exact integral of x^i y^j z^k over the unit cube."""
+    return Fraction(1, (i + 1) * (j + 1) * (k + 1))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_variable_coefficient_energies_on_perturbed_mesh(p):
+    """rho = k = 1 + x sampled at the quadrature points through qpoint_coords.
+
+    For u = a.x + c (in the space on any trilinear mesh), grad u = a, so
+    u^T K u = |a|^2 int (1 + x) = 3/2 |a|^2 and u^T M u = int (1 + x)(a.x + c)^2,
+    both exact under q = p+2 (the integrands have degree <= 5 per reference
+    direction).  The coefficient must reach the right quadrature points: an
+    ordering slip in qpoint_coords (e.g. qz fastest) misses by about 1e-4.
+    """
+    n = 3
+    v = inputs.perturbed_vertices(n, n, n, seed=31 + p)
+    q = p + 2
+    XQ = fem.qpoint_coords(v, n, n, n, q)        # [ne, 3, q^3]
+    kq = 1.0 + XQ[:, 0, :]
+    X = fem.node_coords(v, n, n, n, p)
+    af = (Fraction(3, 10), Fraction(-6, 5), Fraction(7, 10))
+    cf = Fraction(2, 5)
+    a = np.array([float(t) for t in af])
+    c = float(cf)
+    u = X @ a + c
+    K = fem.assemble("diffusion", v, n, n, n, p, coef_q=kq)
+    M = fem.assemble("mass", v, n, n, n, p, coef_q=kq)
+    aa = sum(t * t for t in af)
+    assert abs(u @ (K @ u) - float(Fraction(3, 2) * aa)) < 1e-13
+    # (1 + x)(a1 x + a2 y + a3 z + c)^2 expanded into monomials x^i y^j z^k
+    lin = {(1, 0, 0): af[0], (0, 1, 0): af[1], (0, 0, 1): af[2], (0, 0, 0): cf}
+    sq = {}
+    for m1, c1 in lin.items():
+        for m2, c2 in lin.items():
+            key = tuple(s + t for s, t in zip(m1, m2))
+            sq[key] = sq.get(key, 0) + c1 * c2
+    exact = Fraction(0)
+    for (i, j, k), cc in sq.items():
+        exact += cc * (_cube_moment(i, j, k) + _cube_moment(i + 1, j, k))
+    assert abs(u @ (M @ u) - float(exact)) < 1e-13
+    # a constant coefficient through the same path is the plain operator scaled
+    K2 = fem.assemble("diffusion", v, n, n, n, p, coef_q=np.full_like(kq, 2.0))
+    K1 = fem.assemble("diffusion", v, n, n, n, p)
+    assert abs(K2 - 2.0 * K1).max() < 1e-14 * abs(K1).max()
+
+
+def test_qpoint_coords_affine_closed_form():
+    """On the unperturbed lattice, point (qx, qy, qz) of element (ex, ey, ez) sits at
+    ((ex + t_qx)/nx, (ey + t_qy)/ny, (ez + t_qz)/nz) with t the Gauss points on [0,1]."""
+    nx, ny, nz, q = 3, 2, 4, 5
+    v = inputs.perturbed_vertices(nx, ny, nz, seed=None)
+    XQ = fem.qpoint_coords(v, nx, ny, nz, q)
+    t, _ = np.polynomial.legendre.leggauss(q)
+    t = (t + 1) / 2
+    e = 0
+    for ez in range(nz):
+        for ey in range(ny):
+            for ex in range(nx):
+                m = 0
+                for qz in range(q):
+                    for qy in range(q):
+                        for qx in range(q):
+                            want = ((ex + t[qx]) / nx, (ey + t[qy]) / ny, (ez + t[qz]) / nz)
+                            np.testing.assert_allclose(XQ[e, :, m], want, atol=1e-15)
+                            m += 1
+                e += 1
+
+
 def _brute_element(v8, p, q, kind):
     """Scalar triple loop over (i, j, point) with its own Lagrange, Jacobian and inverse (adjugate)."""
     nodes = list(fem.gll_nodes(p))
@@ -367,14 +436,55 @@ def test_pcg_matches_direct_solve():
 
 
 def test_poisson_config_small_affine():
-    """4^3 affine mesh, p = 2, q = 4: converges to 1e-10, solution close to sin sin sin."""
+    """4^3 affine mesh, p = 2, q = 4, manufactured sine solution, Jacobi-PCG to 1e-10.
+
+    The expected values come from an independent script that assembled the same
+    problem in Kronecker form (1D matrices, no element loop) and ran its own
+    Jacobi-PCG: 4 iterations, max nodal error 1.1683e-3 against sin sin sin, and
+    discrete energy u_h^T K u_h = 3.699126 (the continuous one is 3 pi^2 / 8 =
+    3.701102).  A dropped Jacobi scaling, a wrong right-hand side or a wrong
+    stopping rule changes at least one of them.
+    """
     n, p = 4, 2
     v = inputs.perturbed_vertices(n, n, n, seed=None)
     res = fem.solve_poisson(v, n, n, n, p, f=inputs.f_manufactured, rtol=1e-10)
     X = fem.node_coords(v, n, n, n, p)
-    err = np.abs(res["x"] - inputs.u_exact(X[:, 0], X[:, 1], X[:, 2])).max()
-    assert res["rel_res"] <= 1e-10 and res["iterations"] < 50
-    assert err < 2e-3
+    x = res["x"]
+    err = np.abs(x - inputs.u_exact(X[:, 0], X[:, 1], X[:, 2])).max()
+    assert res["rel_res"] <= 1e-10 and res["true_rel_res"] <= 1e-10
+    assert res["iterations"] == 4
+    assert abs(err - 1.1683e-3) <= 1e-7, err
+    assert abs(x @ (res["A"] @ x) - 3.699126) <= 1e-6
+    assert abs(3 * math.pi ** 2 / 8 - 3.701102) < 1e-6  # the continuous energy quoted above
+
+
+def test_pcg_iterate_is_krylov_energy_minimizer():
+    """The k-th Jacobi-PCG iterate minimizes the A-norm error over x0 + K_k(D^-1 A, D^-1 r0).
+
+    That characterization of preconditioned CG does not use its recurrences: the
+    minimizer is computed here from an explicit Krylov basis and a small dense
+    solve.  A wrong preconditioner (scaling, transposition) changes the space.
+    """
+    rng = np.random.default_rng(17)
+    m = 12
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    S = Q @ np.diag(np.linspace(1.0, 30.0, m)) @ Q.T
+    Dh = np.diag(rng.uniform(0.5, 3.0, m))
+    A = sp.csr_matrix(Dh @ S @ Dh)  # SPD with a non-constant diagonal
+    b = rng.standard_normal(m)
+    dinv = 1.0 / A.diagonal()
+    for k in (1, 2, 3, 5):
+        xk, it, _ = fem.pcg(A, b, dinv, rtol=1e-300, maxit=k)
+        assert it == k
+        Ad = A.toarray()
+        V = np.empty((m, k))
+        v = dinv * b
+        for j in range(k):
+            V[:, j] = v
+            v = dinv * (Ad @ v)
+        V, _ = np.linalg.qr(V)
+        y = np.linalg.solve(V.T @ Ad @ V, V.T @ b)
+        np.testing.assert_allclose(xk, V @ y, rtol=1e-9, atol=1e-12)
 
 
 @pytest.mark.parametrize("p", [1, 2])
