@@ -208,8 +208,9 @@ int pafem_rhs_assemble(pafem_op* op, const double* f_qpts_dev, double* b_dev, vo
 /* ---- solve ------------------------------------------------------------------- */
 typedef struct {
   int mode;          /* PAFEM_SOLVE_* */
-  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for plain CG;
-                        MIXED: confirmed on the FP64 residual) */
+  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2, confirmed in every mode on the
+                        residual recomputed in FP64 (plain CG restarts from x with that
+                        residual when the recursive one meets rtol first) */
   double inner_rtol; /* IR: relative tolerance of each FP32 inner solve (e.g. 1e-4);
                         MIXED: residual drop that triggers a replacement, in (0, 1) (e.g. 0.1) */
   int maxit;         /* plain, MIXED: max CG iterations; IR: max inner iterations per solve */
@@ -219,8 +220,9 @@ typedef struct {
 
 typedef struct {
   int iterations;       /* plain, MIXED: CG iterations; IR: total inner iterations */
-  int outer_iterations; /* IR: refinement steps; MIXED: residual replacements (0 for plain) */
-  double rel_res;       /* final relative residual the stopping test saw */
+  int outer_iterations; /* IR: refinement steps; MIXED: residual replacements; plain: restarts
+                           from the FP64 residual */
+  double rel_res;       /* final relative residual of the last CG recursion */
   double true_rel_res;  /* ||b - A x||_2 / ||b||_2 recomputed in FP64 after the solve */
   double seconds;       /* wall time of the solve on the host clock */
 } pafem_solve_stats;

@@ -304,7 +304,7 @@ def test_poisson_perturbed_plain_and_mixed(pf, ctx, p):
     for mode, inner in ((pf.SOLVE_PLAIN_FP64, 1e-3), (pf.SOLVE_IR_FP32, 1e-3),
                         (pf.SOLVE_MIXED_FP32, 0.1)):
         x, st = op.solve(b, mode=mode, rtol=1e-10, inner_rtol=inner)
-        assert st["true_rel_res"] <= 1.5e-10, (mode, st)
+        assert st["true_rel_res"] <= 1e-10, (mode, st)
         err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
         assert err <= 1e-8, (mode, err)
         its[mode] = st["iterations"]
@@ -562,7 +562,7 @@ def test_fused_cg_step_matches_separate_kernels(pf, ctx, p):
         for im in (pf.INDEX_LATTICE, pf.INDEX_MAP):
             op.set_restriction_mode(im)
             x, st = op.solve(b, x0.clone(), mode=mode, rtol=1e-10, inner_rtol=inner)
-            assert st["true_rel_res"] <= 1.5e-10, (mode, im, st)
+            assert st["true_rel_res"] <= 1e-10, (mode, im, st)
             out[im] = (x, st["iterations"])
         (xl, il), (xm, im_) = out[pf.INDEX_LATTICE], out[pf.INDEX_MAP]
         assert abs(il - im_) <= 1, (mode, il, im_)
@@ -588,7 +588,42 @@ def test_fused_cg_full_size_matches_separate_kernels(pf, ctx):
                              raise_on_nonconvergence=False)
             assert st["iterations"] == 30
             out[im] = (x, st["rel_res"])
+            if mode == pf.SOLVE_PLAIN_FP64:
+                # the CG invariant: the recursively updated residual is b - A x
+                # recomputed through the apply that the sampled-row tests pin
+                # to the oracle
+                assert abs(st["true_rel_res"] - st["rel_res"]) <= 1e-8 * st["rel_res"], (im, st)
         (xl, rl), (xm, rm) = out[pf.INDEX_LATTICE], out[pf.INDEX_MAP]
         assert ((xl - xm).norm() / xm.norm()).item() < tol, mode
         assert abs(rl - rm) <= tol * rm, (mode, rl, rm)
     op.set_restriction_mode(pf.INDEX_LATTICE)
+
+
+def test_fused_cg_full_size_solves_to_tolerance(pf, ctx):
+    """One fused FP64 Jacobi-PCG solve to 1e-10 at the full 7.9M-dof p=6 size
+    (grid-stride branch of the fused E^T step and the wide alpha reduction):
+    the residual recomputed in FP64 meets the tolerance, and the solution is
+    close to the manufactured one (discretization error, not solver error)."""
+    n, p = 33, 6
+    v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
+    sp_ = pf.Space(pf.Mesh(ctx, n, n, n, v), p)
+    op = pf.Operator(sp_, pf.DIFFUSION)
+    op.assemble(pf.FP64)
+    b = op.rhs()
+    x, st = op.solve(b, rtol=1e-10, check_every=50)
+    assert st["true_rel_res"] <= 1e-10, st
+    assert st["rel_res"] <= 1e-10, st
+    # sampled nodal values against u = sin sin sin at the GLL nodes of a few elements
+    xn = x.cpu().numpy()
+    rng = np.random.default_rng(4)
+    for e in rng.integers(0, n ** 3, 6):
+        ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+        vv = v.reshape(n + 1, n + 1, n + 1, 3)
+        v8 = np.array([vv[ez + k, ey + j, ex + i] for k in (0, 1) for j in (0, 1) for i in (0, 1)])
+        Xn, _ = fem.trilinear(v8, fem.tensor_points(fem.gll_nodes(p)))
+        E = fem.element_restriction(1, 1, 1, p)[0]  # local lattice offsets of one element
+        L = n * p + 1
+        loc = E % (p + 1) + L * ((E // (p + 1)) % (p + 1)) + L * L * (E // (p + 1) ** 2)
+        g = (ex * p) + L * (ey * p) + L * L * (ez * p) + loc
+        ue = inputs.u_exact(Xn[:, 0], Xn[:, 1], Xn[:, 2])
+        assert np.abs(xn[g] - ue).max() < 1e-6
