@@ -99,7 +99,8 @@ const char* pafem_last_error(void);
 int pafem_version(void);
 
 /* ---- context ---------------------------------------------------------------- */
-/* Bind to HIP device `device` (>= 0), or host-only with device = -1.
+/* Bind to HIP device `device` (>= 0), or host-only with device = -1.  (No
+ * counterpart in the paper: the device binding of everything below.)
  * Errors: NO_DEVICE if the device does not exist, HIP on runtime failure. */
 int pafem_ctx_create(int device, pafem_ctx** out);
 int pafem_ctx_destroy(pafem_ctx* ctx);
@@ -109,13 +110,20 @@ int pafem_ctx_destroy(pafem_ctx* ctx);
  * vertices are given, x index fastest: vert_xyz_host[((k (ny+1) + j) (nx+1) + i) * 3 + d].
  * Element (ex,ey,ez) has corners (ex+i, ey+j, ez+k), i,j,k in {0,1}; the map
  * from [0,1]^3 is trilinear.  The array is copied (to the device too, for a
- * GPU context).  Orientation is checked later, at operator assembly. */
+ * GPU context).  Orientation is checked later, at operator assembly.
+ * Defined by: the mesh layer of the paper (section "Meshing"), whose element
+ * maps carry the local Jacobian used in "High-order mesh optimization"; here
+ * that Jacobian is the one of the trilinear map, evaluated at every
+ * quadrature point by pafem_op_assemble. */
 int pafem_mesh_create_structured(pafem_ctx* ctx, int nx, int ny, int nz,
                                  const double* vert_xyz_host, pafem_mesh** out);
 int pafem_mesh_destroy(pafem_mesh* mesh);
 
 /* ---- order p: H1 space and its integer maps ----------------------------------- */
-/* Order p in 1..8 (INVALID_ARG otherwise).  Builds the element restriction E
+/* Defined by: the operator decomposition figure ("finite element operator
+ * decomposition"), whose G takes the L-vector of global dofs to the E-vector
+ * of element dofs; it is topological, so here it is the lattice numbering.
+ * Order p in 1..8 (INVALID_ARG otherwise).  Builds the element restriction E
  * (int32, [ne][(p+1)^3]), its transpose in CSR form and the essential-dof list;
  * ne*(p+1)^3 and the dof count must each fit in int32 (INVALID_ARG otherwise). */
 int pafem_space_create(pafem_mesh* mesh, int p, pafem_space** out);
@@ -134,14 +142,20 @@ int pafem_space_get_restriction_transpose(const pafem_space* space, int32_t* off
 int pafem_space_get_ess_dofs(const pafem_space* space, int32_t* out_host);
 
 /* ---- quadrature: 1D tables (host, no GPU needed) ------------------------------ */
-/* Gauss-Lobatto-Legendre nodes (p+1), Gauss-Legendre points and weights (q) on
+/* Defined by: the B of the operator decomposition figure (element dofs to
+ * quadrature-point values), applied one direction at a time (sum
+ * factorization, section "Matrix-free solvers for high-order finite elements").
+ * Gauss-Lobatto-Legendre nodes (p+1), Gauss-Legendre points and weights (q) on
  * [0,1], and B[qq][a] = l_a(x_qq), G[qq][a] = l_a'(x_qq) (row-major [q][p+1]).
  * Any output pointer may be NULL.  1 <= p <= 8, 1 <= q <= 12. */
 int pafem_basis_tables(int p, int q, double* gll_nodes, double* gl_points, double* gl_weights,
                        double* B, double* G);
 
 /* ---- operator --------------------------------------------------------------- */
-/* Create a MASS or DIFFUSION operator on `space` with q1d points per direction
+/* Defined by: the operator decomposition figure (A = P^T G^T B^T D B G P) for
+ * the mass and diffusion forms (the paper's BP1 and BP3 benchmarks, section
+ * "State-of-the-art performance on exascale platforms and AMD GPUs").
+ * Create a MASS or DIFFUSION operator on `space` with q1d points per direction
  * (0 = default p+2; any other value but p+2 gives UNSUPPORTED).  The
  * coefficient defaults to the constant 1.  Nothing is computed until
  * pafem_op_assemble. */
@@ -150,14 +164,21 @@ int pafem_op_destroy(pafem_op* op);
 int pafem_op_q1d(const pafem_op* op);
 /* Physical coordinates of the quadrature points, xyz_dev[ne][3][q^3] (double). */
 int pafem_op_qpoint_coords(pafem_op* op, double* xyz_dev, void* stream);
-/* Coefficient (rho for MASS, k for DIFFUSION): a constant, values at the
+/* Defined by: the pointwise D of the operator decomposition figure, which
+ * holds the coefficient at the quadrature points; user-supplied variable
+ * coefficients follow section "Python interface (PyMFEM)", evaluated here by
+ * the caller at the points pafem_op_qpoint_coords returns (no callbacks).
+ * Coefficient (rho for MASS, k for DIFFUSION): a constant, values at the
  * quadrature points k_dev[ne][q^3] (copied into library memory on `stream`),
  * or the built-in k = 1 + amp sin(2 pi x) evaluated on the device. Takes effect
  * at the next pafem_op_assemble. */
 int pafem_op_set_coefficient_const(pafem_op* op, double c);
 int pafem_op_set_coefficient_qpts(pafem_op* op, const double* k_dev, void* stream);
 int pafem_op_set_coefficient_sinx(pafem_op* op, double amp);
-/* Compute the quadrature data D on the device (synchronous).
+/* Defined by: the partial assembly level of section "State-of-the-art
+ * performance on exascale platforms and AMD GPUs" (only the data at the
+ * quadrature points is precomputed and stored).
+ * Compute the quadrature data D on the device (synchronous).
  * MASS: D[e][0][qpt] = w rho detJ.  DIFFUSION: D[e][0..5][qpt] = the upper
  * triangle xx,xy,xz,yy,yz,zz of w k adj(J) adj(J)^T / detJ.  FP64 is always
  * built; prec_mask | PAFEM_FP32 also keeps an FP32 rounded copy and
@@ -177,7 +198,9 @@ int pafem_op_set_scatter_mode(pafem_op* op, int mode);
  * return).  Both give identical results. */
 int pafem_op_set_restriction_mode(pafem_op* op, int mode);
 
-/* y = A x.  prec selects double (PAFEM_FP64) or float vectors of length ndofs
+/* Defined by: the operator decomposition figure, y = G^T B^T D B G x (P is
+ * the identity on one GPU), at the partial assembly level.
+ * y = A x.  prec selects double (PAFEM_FP64) or float vectors of length ndofs
  * with the FP32 (PAFEM_FP32) or bfloat16 (PAFEM_BF16) quadrature data; the
  * contractions then run in FP32.  x and y must not alias.  flags:
  *   0: the plain assembled operator;
@@ -187,18 +210,24 @@ int pafem_op_set_restriction_mode(pafem_op* op, int mode);
  *     the default atomic E^T mode this launches the element kernel alone). */
 int pafem_op_apply(pafem_op* op, int prec, const void* x_dev, void* y_dev, int flags,
                    void* stream);
-/* The element results before assembly: yE_dev[e][l] = (B^T D B E x)_e at local
+/* Defined by: the E-vector of the operator decomposition figure (before G^T).
+ * The element results before assembly: yE_dev[e][l] = (B^T D B E x)_e at local
  * node l = a + (p+1)(b + (p+1)c), an E-vector of ne*(p+1)^3 entries of the
  * precision `prec` (one element kernel, no E^T).  flags: 0 or
  * PAFEM_APPLY_CONSTRAINED (essential entries of x read as 0). */
 int pafem_op_apply_evector(pafem_op* op, int prec, const void* x_dev, void* yE_dev, int flags,
                            void* stream);
-/* d = diag(A) by sum factorization (double, ndofs); constrained = 1 puts 1 on
+/* Defined by: section "Matrix-free solvers for high-order finite elements"
+ * (the diagonal of the operator computed by sum factorization without
+ * assembling the matrix, for diagonal smoothers and Jacobi).
+ * d = diag(A) by sum factorization (double, ndofs); constrained = 1 puts 1 on
  * essential dofs.  Bitwise reproducible. */
 int pafem_op_diagonal(pafem_op* op, double* d_dev, int constrained, void* stream);
 
 /* ---- right-hand side ------------------------------------------------------------ */
-/* b_i = sum_e sum_q w detJ f(x_q) phi_i(x_q) with the op's quadrature rule and
+/* (The paper states no right-hand side; this is the load of the manufactured
+ * Poisson problem, integrated with the operator's own quadrature.)
+ * b_i = sum_e sum_q w detJ f(x_q) phi_i(x_q) with the op's quadrature rule and
  * geometry; f_qpts_dev[ne][q^3] holds f at the quadrature points (as returned
  * by pafem_op_qpoint_coords), or NULL for the built-in f = 3 pi^2
  * sin(pi x) sin(pi y) sin(pi z).  Essential entries of b are set to 0.
@@ -227,7 +256,11 @@ typedef struct {
   double seconds;       /* wall time of the solve on the host clock */
 } pafem_solve_stats;
 
-/* Solve A x = b for the constrained operator of `op` (DIFFUSION or MASS) with
+/* Defined by: section "Matrix-free solvers for high-order finite elements"
+ * (a Krylov method with a preconditioner built without the assembled matrix,
+ * here CG with the sum-factorized diagonal); the fused iteration follows
+ * section "Kernel fusion".  The mixed-precision modes are not in the paper.
+ * Solve A x = b for the constrained operator of `op` (DIFFUSION or MASS) with
  * Jacobi preconditioning; x_dev holds the initial guess on entry (its
  * essential entries must equal b's) and the solution on return.
  * Synchronous.  NOT_CONVERGED if the iteration limit is hit (x then holds the
@@ -237,7 +270,9 @@ int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem
                    pafem_solve_stats* stats, void* stream);
 
 /* ---- reductions (exposed for testing the CG building blocks) --------------------- */
-/* result_dev[0] = sum_i x[i] y[i] over n doubles, fixed-order two-stage
+/* Defined by: section "Kernel fusion" (dot products reduced with wavefront-
+ * level instructions).
+ * result_dev[0] = sum_i x[i] y[i] over n doubles, fixed-order two-stage
  * reduction (bitwise reproducible for a given n); x, y may be NULL when n = 0. */
 int pafem_dot(pafem_ctx* ctx, int64_t n, const double* x_dev, const double* y_dev,
               double* result_dev, void* stream);
