@@ -217,6 +217,20 @@ int pafem_op_apply(pafem_op* op, int prec, const void* x_dev, void* y_dev, int f
  * PAFEM_APPLY_CONSTRAINED (essential entries of x read as 0). */
 int pafem_op_apply_evector(pafem_op* op, int prec, const void* x_dev, void* yE_dev, int flags,
                            void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): pafem_op_apply
+ * with the same arguments, flags and results, always with the deterministic
+ * E^T on the lattice numbering (bitwise equal to pafem_op_apply in the default
+ * modes), whose E-vector workspace is a fixed device array of
+ * PAFEM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  Nothing is allocated and no library routine that
+ * allocates is called.  INVALID_ARG, before anything is enqueued, when the
+ * workspace the operator needs (ne (p+1)^3 words of the vector type) exceeds
+ * the array.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race. */
+#define PAFEM_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+int pafem_op_apply_noalloc(pafem_op* op, int prec, const void* x_dev, void* y_dev, int flags,
+                           void* stream);
 /* Defined by: section "Matrix-free solvers for high-order finite elements"
  * (the diagonal of the operator computed by sum factorization without
  * assembling the matrix, for diagonal smoothers and Jacobi).

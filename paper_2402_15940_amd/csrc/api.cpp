@@ -191,27 +191,33 @@ ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* sk
 }
 
 template <typename T>
-int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s, int qprec) {
+int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s, int qprec,
+               void* work) {
   Space* sp = op->space;
   const int n = sp->p + 1;
+  if (work != nullptr) {
+    // caller-provided E-vector workspace: the deterministic E^T on the
+    // lattice numbering, nothing allocated (the maps are not needed)
+    ApplyArgs<T> a = make_args<T>(op, x, y, static_cast<T*>(work), flags, skip, qprec);
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, kScatterXRows, PAFEM_INDEX_LATTICE, a, s));
+    PAFEM_TRY_HIP(launch_gather_xrows<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
+                                         a.accumulate, x, y, skip, s));
+    return PAFEM_OK;
+  }
   const int im = op->index_mode;
   if (im == PAFEM_INDEX_MAP) PAFEM_TRY(ensure_device_maps(sp));
   if (op->scatter_mode == PAFEM_SCATTER_ATOMIC && (flags & PAFEM_APPLY_CONSTRAINED))
     PAFEM_TRY(ensure_ess(sp, true));
   if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
     PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
+    if (im == PAFEM_INDEX_LATTICE)
+      return apply_impl<T>(op, x, y, flags, skip, s, qprec, op->d_evec.ptr);
     // element pass into the E-vector, then the ordered per-node sum
     ApplyArgs<T> a = make_args<T>(op, x, y, op->d_evec.as<T>(), flags, skip, qprec);
-    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q,
-                                  im == PAFEM_INDEX_MAP ? kScatterEvector : kScatterXRows, im, a, s));
-    if (im == PAFEM_INDEX_MAP) {
-      PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(),
-                                        sp->d_et_idx.as<int32_t>(), a.ess_mask, a.constrained,
-                                        a.accumulate, x, y, sp->ndofs, skip, s));
-    } else {
-      PAFEM_TRY_HIP(launch_gather_xrows<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
-                                           a.accumulate, x, y, skip, s));
-    }
+    PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, kScatterEvector, im, a, s));
+    PAFEM_TRY_HIP(launch_gather_et<T>(a.yE, sp->d_et_off.as<int32_t>(), sp->d_et_idx.as<int32_t>(),
+                                      a.ess_mask, a.constrained, a.accumulate, x, y, sp->ndofs,
+                                      skip, s));
   } else {
     ApplyArgs<T> a = make_args<T>(op, x, y, nullptr, flags, skip, qprec);
     // zero y with a kernel (not a memset) so the sequence can sit in a captured graph
@@ -280,8 +286,10 @@ int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
   return gather_full(op, op->d_evec.as<double>(), 0, d, s);
 }
 
-template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t, int);
-template int apply_impl<float>(Op*, const float*, float*, int, const int*, hipStream_t, int);
+template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t, int,
+                                void*);
+template int apply_impl<float>(Op*, const float*, float*, int, const int*, hipStream_t, int,
+                               void*);
 
 }  // namespace pafem
 
@@ -355,6 +363,11 @@ int pafem_ctx_create(int device, pafem_ctx** out) {
       delete c;
       set_error(std::string("device setup: ") + hipGetErrorString(e));
       return PAFEM_ERR_HIP;
+    }
+    const int rc = noalloc_init(device);
+    if (rc != PAFEM_OK) {
+      delete c;
+      return rc;
     }
   }
   *out = c;

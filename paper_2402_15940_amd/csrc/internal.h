@@ -173,10 +173,16 @@ int ensure_host_maps(Space* sp);
 int ensure_device_maps(Space* sp);
 int ensure_ess(Space* sp, bool device);
 // qprec selects the stored quadrature data for float vectors: PAFEM_FP32 or PAFEM_BF16.
+// With `work` (at least apply_work_bytes) the deterministic E^T on the lattice
+// numbering runs with that E-vector workspace and nothing is allocated;
+// otherwise the op's scatter and restriction modes apply.
 template <typename T>
 int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t s,
-               int qprec = 0);
+               int qprec = 0, void* work = nullptr);
 int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s);
+// Device address of the allocation-free apply's workspace on `device` (current),
+// looked up once per device (noalloc.hip).
+int noalloc_init(int device);
 
 // ---------------------------------------------------------------------------
 // kernel launchers (k_*.hip)
@@ -258,6 +264,12 @@ __host__ __device__ constexpr int xrows_width(int n) { return n == 7 ? PAFEM_XRO
 
 // Words of an E-vector buffer for either layout: ne (p+1)^2 max(p+1, width).
 inline int64_t evec_words(int64_t ne, int n) { return ne * n * n * xrows_width(n); }
+
+// Bytes of E-vector workspace one apply with elements of type T needs.
+template <typename T>
+inline int64_t apply_work_bytes(const Op* op) {
+  return evec_words(op->space->ne, op->space->p + 1) * (int64_t)sizeof(T);
+}
 
 // Offset of local node (a, b, c) of element (ex, ey, ez) in the x-interleaved
 // layout (< evec_words < 2^31).

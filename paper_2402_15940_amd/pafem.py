@@ -124,6 +124,7 @@ _SIGNATURES = {
     "pafem_op_set_restriction_mode": (_I, [_P, _I]),
     "pafem_op_apply": (_I, [_P, _I, _P, _P, _I, _P]),
     "pafem_op_apply_evector": (_I, [_P, _I, _P, _P, _I, _P]),
+    "pafem_op_apply_noalloc": (_I, [_P, _I, _P, _P, _I, _P]),
     "pafem_op_diagonal": (_I, [_P, _P, _I, _P]),
     "pafem_rhs_assemble": (_I, [_P, _P, _P, _P]),
     "pafem_solve_cg": (_I, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveStats), _P]),
@@ -394,6 +395,17 @@ class Operator:
         flags = (APPLY_CONSTRAINED if constrained else 0) | (APPLY_ACCUMULATE if accumulate else 0)
         _check(lib().pafem_op_apply(self._h, prec, _dptr(x, x.dtype, n, "x"),
                                     _dptr(y, x.dtype, n, "y"), flags, _stream(stream)))
+        return y
+
+    def apply_noalloc(self, x, y, constrained: bool = False, accumulate: bool = False,
+                      bf16: bool = False, stream=None):
+        """y = A x through the allocation-free entry point (y must be given)."""
+        torch = self._torch()
+        prec = FP64 if x.dtype == torch.float64 else (BF16 if bf16 else FP32)
+        n = self.space.ndofs
+        flags = (APPLY_CONSTRAINED if constrained else 0) | (APPLY_ACCUMULATE if accumulate else 0)
+        _check(lib().pafem_op_apply_noalloc(self._h, prec, _dptr(x, x.dtype, n, "x"),
+                                            _dptr(y, x.dtype, n, "y"), flags, _stream(stream)))
         return y
 
     def apply_evector(self, x, yE=None, constrained: bool = False, bf16: bool = False,
