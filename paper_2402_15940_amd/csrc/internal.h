@@ -262,6 +262,28 @@ constexpr int kScatterXRowsDot = 4;
 #endif
 __host__ __device__ constexpr int xrows_width(int n) { return n == 7 ? PAFEM_XROWS_PAD7 : n; }
 
+// Division of a non-negative 31-bit integer by a divisor d >= 2 fixed at
+// launch, as a multiply-high and a shift (no integer divide instruction on
+// the GPU): with s = ceil(log2 d) and m = ceil(2^(31+s) / d) < 2^32,
+// floor(n / d) = floor(n m / 2^(31+s)) exactly for 0 <= n < 2^31, since
+// m d - 2^(31+s) < d <= 2^s makes the excess of n m / 2^(31+s) over n / d
+// smaller than 1/d.
+struct FastDiv {
+  uint32_t m = 0;
+  int s = 1;
+  int d = 2;
+  FastDiv() = default;
+  explicit FastDiv(int divisor) : d(divisor) {
+    s = 0;
+    while ((1LL << s) < (long long)divisor) ++s;
+    const unsigned long long num = 1ULL << (31 + s);
+    m = (uint32_t)((num + (unsigned long long)divisor - 1) / (unsigned long long)divisor);
+  }
+  __host__ __device__ __forceinline__ int div(int n) const {
+    return (int)((uint32_t)(((uint64_t)(uint32_t)n * m) >> 32) >> (s - 1));
+  }
+};
+
 // Words of an E-vector buffer for either layout: ne (p+1)^2 max(p+1, width).
 inline int64_t evec_words(int64_t ne, int n) { return ne * n * n * xrows_width(n); }
 

@@ -70,68 +70,129 @@ __global__ __launch_bounds__(kThreads) void k_gather_lattice(const T* __restrict
 // (element, local node) order: for every (z, y) candidate in ascending order,
 // element ex-1 before element ex (the order of the stored map's CSR sum, so
 // the lattice and map forms agree bitwise).
+//
+// The row and plane of a node come from divisions by the lattice extents,
+// fixed at launch (FastDiv: a multiply-high and a shift).  Along y (and z)
+// the candidates of lattice coordinate J are the element ey = min(J / p,
+// ny - 1) at local index ly = J - ey p and, when ly = 0 and ey > 0, also
+// element ey - 1 at local index p; their runs sit N^2 - p runs apart (N (ny N
+// - p) along z for the planes), so one base offset and two strides address
+// all four (y, z) runs.  The y/z branches are uniform over a wavefront except
+// where it crosses a row; the x-face word is loaded by every lane (the node's
+// own word when it is not on an x face) and selected.
 constexpr int kXRowsNodes = 2;
 
+struct XRowsGeom {
+  int nx, ny, nz;
+  int Lx, Ly, Lz;
+  FastDiv fLx, fLy;
+  int64_t n;
+};
+
+inline XRowsGeom xrows_geom(int nx, int ny, int nz, int p) {
+  XRowsGeom g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.Lx = nx * p + 1;
+  g.Ly = ny * p + 1;
+  g.Lz = nz * p + 1;
+  g.fLx = FastDiv(g.Lx);
+  g.fLy = FastDiv(g.Ly);
+  g.n = (int64_t)g.Lx * g.Ly * g.Lz;
+  return g;
+}
+
+// The loaded contributions of one node and what decides its sum.
+template <typename T>
+struct XRowsLoads {
+  T v[4], w[4];  // (z, y) candidates 0: (right, right) 1: (right, left) 2: (left, right) 3: (left, left)
+  bool hy, hz, xf, ess;
+};
+
 template <typename T, int P>
-__global__ __launch_bounds__(kThreads) void k_gather_xrows(
-    const T* __restrict__ yX, int nx, int ny, int nz, int constrained, int accumulate,
-    const T* __restrict__ x, T* __restrict__ y, const int* skip) {
-  constexpr int N = P + 1, R = kXRowsNodes, W = xrows_width(N);
+__device__ __forceinline__ void xrows_load(const T* __restrict__ yX, const XRowsGeom& g, int i,
+                                           XRowsLoads<T>& L) {
+  constexpr int N = P + 1, W = xrows_width(N);
+  const int row = g.fLx.div(i), I = i - row * g.Lx;
+  const int K = g.fLy.div(row), J = row - K * g.Ly;
+  int ex = I / P, a = I - ex * P;
+  if (ex == g.nx) {  // the row's last node
+    ex = g.nx - 1;
+    a = P;
+  }
+  int ey = J / P, ez = K / P;
+  ey = ey < g.ny - 1 ? ey : g.ny - 1;
+  ez = ez < g.nz - 1 ? ez : g.nz - 1;
+  const int ly = J - ey * P, lz = K - ez * P;
+  L.hy = ly == 0 && ey > 0;
+  L.hz = lz == 0 && ez > 0;
+  L.xf = a == 0 && ex > 0;
+  L.ess = I == 0 || I == g.Lx - 1 || J == 0 || J == g.Ly - 1 || K == 0 || K == g.Lz - 1;
+  const int rowlen = g.nx * W;
+  const int o = (((ez * g.ny + ey) * N + lz) * N + ly) * rowlen + ex * W + a;
+  const int dy = (N * N - P) * rowlen, dz = N * (g.ny * N - P) * rowlen;
+  const int left = L.xf ? P - W : 0;
+  L.v[0] = yX[o];
+  L.w[0] = yX[o + left];
+  if (L.hy) {
+    L.v[1] = yX[o - dy];
+    L.w[1] = yX[o - dy + left];
+  }
+  if (L.hz) {
+    L.v[2] = yX[o - dz];
+    L.w[2] = yX[o - dz + left];
+    if (L.hy) {
+      L.v[3] = yX[o - dz - dy];
+      L.w[3] = yX[o - dz - dy + left];
+    }
+  }
+}
+
+// Sum of the loaded contributions in ascending (element, local node) order.
+template <typename T>
+__device__ __forceinline__ T xrows_sum(const XRowsLoads<T>& L) {
+  T acc = 0;
+  if (L.hz) {
+    if (L.hy) {
+      if (L.xf) acc += L.w[3];
+      acc += L.v[3];
+    }
+    if (L.xf) acc += L.w[2];
+    acc += L.v[2];
+  }
+  if (L.hy) {
+    if (L.xf) acc += L.w[1];
+    acc += L.v[1];
+  }
+  if (L.xf) acc += L.w[0];
+  acc += L.v[0];
+  return acc;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__ yX, XRowsGeom g,
+                                                           int constrained, int accumulate,
+                                                           const T* __restrict__ x,
+                                                           T* __restrict__ y, const int* skip) {
+  constexpr int R = kXRowsNodes;
   if (skip != nullptr && *skip) return;
-  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1;
-  const int64_t n = (int64_t)Lx * Ly * Lz;
   const int64_t base = (int64_t)blockIdx.x * (kThreads * R) + threadIdx.x;
-  T v[R][4], w[R][4];
-  int cy[R], cz[R], Iq[R], Jq[R], Kq[R];
-  bool xf[R];
+  XRowsLoads<T> L[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int64_t iq = base + q * kThreads;
-    const int i = (int)(iq < n ? iq : n - 1);
-    const int row = i / Lx, I = i - row * Lx, J = row % Ly, K = row / Ly;
-    int ex = I / P, a = I - ex * P;
-    if (ex == nx) {  // the row's last node
-      ex = nx - 1;
-      a = P;
-    }
-    const bool xface = a == 0 && ex > 0;
-    const int col = ex * W + a, left = xface ? P - W : 0;
-    int ey[2], ly[2], ez[2], lz[2];
-    cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
-    cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
-#pragma unroll
-    for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-      for (int ky = 0; ky < 2; ++ky) {
-        const int k = 2 * kz + ky;
-        const bool on = kz < cz[q] && ky < cy[q];
-        const T* r = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
-        v[q][k] = on ? r[0] : T(0);
-        w[q][k] = (on && xface) ? r[left] : T(0);
-      }
-    Iq[q] = I;
-    Jq[q] = J;
-    Kq[q] = K;
-    xf[q] = xface;
+    xrows_load<T, P>(yX, g, (int)(iq < g.n ? iq : g.n - 1), L[q]);
   }
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int64_t i = base + q * kThreads;
-    if (i >= n) break;
-    const int I = Iq[q], J = Jq[q], K = Kq[q];
-    T acc = 0;
-    if (constrained && (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1)) {
+    if (i >= g.n) break;
+    T acc;
+    if (constrained && L[q].ess)
       acc = x ? x[i] : T(0);
-    } else {
-#pragma unroll
-      for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-        for (int ky = 0; ky < 2; ++ky)
-          if (kz < cz[q] && ky < cy[q]) {
-            if (xf[q]) acc += w[q][2 * kz + ky];
-            acc += v[q][2 * kz + ky];
-          }
-    }
+    else
+      acc = xrows_sum(L[q]);
     y[i] = accumulate ? y[i] + acc : acc;
   }
 }
@@ -144,70 +205,28 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows(
 // the solution (FP64 for mixed CG).
 template <typename T, typename TX, int P>
 __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
-    const T* __restrict__ yX, int nx, int ny, int nz, const T* __restrict__ p, TX* __restrict__ x,
+    const T* __restrict__ yX, XRowsGeom g, const T* __restrict__ p, TX* __restrict__ x,
     T* __restrict__ r, const T* __restrict__ dinv, double* __restrict__ partials,
     const CgState* __restrict__ st) {
-  constexpr int N = P + 1, R = kXRowsNodes, W = xrows_width(N);
+  constexpr int R = kXRowsNodes;
   if (st->done) return;
   const T alpha = (T)st->alpha;
   const double alpha_x = st->alpha;
-  const int Lx = nx * P + 1, Ly = ny * P + 1, Lz = nz * P + 1;
-  const int64_t n = (int64_t)Lx * Ly * Lz;
   double v2[2] = {0.0, 0.0}, out[2];
-  for (int64_t base = (int64_t)blockIdx.x * (kThreads * R) + threadIdx.x; base - threadIdx.x < n;
+  for (int64_t base = (int64_t)blockIdx.x * (kThreads * R) + threadIdx.x; base - threadIdx.x < g.n;
        base += (int64_t)gridDim.x * (kThreads * R)) {
-    T v[R][4], w[R][4];
-    int cy[R], cz[R], Iq[R], Jq[R], Kq[R];
-    bool xf[R];
+    XRowsLoads<T> L[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int64_t iq = base + q * kThreads;
-      const int i = (int)(iq < n ? iq : n - 1);
-      const int row = i / Lx, I = i - row * Lx, J = row % Ly, K = row / Ly;
-      int ex = I / P, a = I - ex * P;
-      if (ex == nx) {
-        ex = nx - 1;
-        a = P;
-      }
-      const bool xface = a == 0 && ex > 0;
-      const int col = ex * W + a, left = xface ? P - W : 0;
-      int ey[2], ly[2], ez[2], lz[2];
-      cy[q] = vec::lattice_cands(J, ny, P, ey, ly);
-      cz[q] = vec::lattice_cands(K, nz, P, ez, lz);
-#pragma unroll
-      for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-        for (int ky = 0; ky < 2; ++ky) {
-          const int k = 2 * kz + ky;
-          const bool on = kz < cz[q] && ky < cy[q];
-          const T* rp = yX + xrows_index(nx, ny, N, 0, ey[ky], ez[kz], 0, ly[ky], lz[kz]) + col;
-          v[q][k] = on ? rp[0] : T(0);
-          w[q][k] = (on && xface) ? rp[left] : T(0);
-        }
-      Iq[q] = I;
-      Jq[q] = J;
-      Kq[q] = K;
-      xf[q] = xface;
+      xrows_load<T, P>(yX, g, (int)(iq < g.n ? iq : g.n - 1), L[q]);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int64_t i = base + q * kThreads;
-      if (i >= n) break;
-      const int I = Iq[q], J = Jq[q], K = Kq[q];
+      if (i >= g.n) break;
       const T pi = p[i];
-      T acc = 0;
-      if (I == 0 || I == Lx - 1 || J == 0 || J == Ly - 1 || K == 0 || K == Lz - 1) {
-        acc = pi;
-      } else {
-#pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-          for (int ky = 0; ky < 2; ++ky)
-            if (kz < cz[q] && ky < cy[q]) {
-              if (xf[q]) acc += w[q][2 * kz + ky];
-              acc += v[q][2 * kz + ky];
-            }
-      }
+      const T acc = L[q].ess ? pi : xrows_sum(L[q]);
       if constexpr (sizeof(TX) == sizeof(T))
         x[i] += alpha * pi;
       else
@@ -553,7 +572,8 @@ hipError_t gather_xrows_p(const T* yX, int nx, int ny, int nz, int constrained, 
   const int64_t nodes = ((int64_t)nx * P + 1) * ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
   const int64_t per = (int64_t)kThreads * kXRowsNodes;
   hipLaunchKernelGGL((k_gather_xrows<T, P>), dim3((unsigned)((nodes + per - 1) / per)),
-                     dim3(kThreads), 0, s, yX, nx, ny, nz, constrained, accumulate, x, y, skip);
+                     dim3(kThreads), 0, s, yX, xrows_geom(nx, ny, nz, P), constrained, accumulate,
+                     x, y, skip);
   return hipGetLastError();
 }
 
@@ -723,7 +743,7 @@ hipError_t gather_xrows_cg_p(const T* yX, int nx, int ny, int nz, const T* p, TX
   if (nblk > kMaxCgParts) nblk = kMaxCgParts;  // the workgroups stride over the rest
   *nparts = (int)nblk;
   hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
-                     yX, nx, ny, nz, p, x, r, dinv, partials, st);
+                     yX, xrows_geom(nx, ny, nz, P), p, x, r, dinv, partials, st);
   return hipGetLastError();
 }
 

@@ -25,3 +25,16 @@ def test_xrows_layout(tmp_path, pad7):
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "bad=0" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"),
+                    reason="needs g++ and the HIP headers")
+def test_fastdiv_matches_integer_division(tmp_path):
+    """The launch-fixed divisions of the E^T sums (FastDiv) are exact on 31-bit numerators."""
+    exe = tmp_path / "fastdiv_check"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    f"-I{CSRC}", os.path.join(HERE, "native", "fastdiv_check.cpp"), "-o", str(exe)],
+                   check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "bad=0" in r.stdout
