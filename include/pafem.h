@@ -283,6 +283,70 @@ typedef struct {
 int pafem_solve_cg(pafem_op* op, const double* b_dev, double* x_dev, const pafem_solve_opts* opts,
                    pafem_solve_stats* stats, void* stream);
 
+/* ---- p-multigrid preconditioned CG ---------------------------------------------- */
+/* Defined by: section "Matrix-free solvers for high-order finite elements" of
+ * the paper (p-multigrid: a hierarchy of polynomial degrees on the same mesh,
+ * transfer between the nested spaces by sum factorization, smoothers built on
+ * the sum-factorized diagonal with Chebyshev acceleration).  The readings
+ * fixed here:
+ *   - orders p, p/2, p/4, ..., 1 (integer halving) on the operator's mesh, each
+ *     level a partial-assembly operator of the same kind and coefficient with
+ *     its own q = p_level + 2 quadrature data (FP64);
+ *   - prolongation: the fine nodal values of the coarse function (sum-factorized
+ *     interpolation from the coarse to the fine GLL nodes); restriction: its
+ *     transpose, with the essential coarse rows set to zero;
+ *   - smoother: `cheb_degree` steps of Chebyshev-accelerated Jacobi for
+ *     D^-1 A on [cheb_lower lmax, lmax], before and after the coarse
+ *     correction (a symmetric V-cycle); lmax = lmax_safety times a
+ *     power-iteration estimate (power_iters steps from a fixed pseudo-random
+ *     vector) unless set with pafem_mg_set_lmax;
+ *   - order-1 level: exactly coarse_iters Jacobi-PCG steps from zero;
+ *   - outer solver: flexible CG (beta = z_new . (r_new - r_old) / z_old . r_old)
+ *     with one V-cycle as preconditioner, stopping like pafem_solve_cg.
+ * Levels are numbered from 0 (the operator's order) to num_levels - 1 (order 1). */
+typedef struct pafem_mg pafem_mg;
+
+typedef struct {
+  int cheb_degree;    /* smoothing steps before and after the coarse correction, 1..16 (3) */
+  double cheb_lower;  /* lower end of the smoothing interval as a fraction of lmax, (0, 1) (0.1) */
+  double lmax_safety; /* factor on the power-iteration estimate, [1, 4] (1.1) */
+  int power_iters;    /* power iterations per smoothed level, >= 1 (10) */
+  int coarse_iters;   /* Jacobi-PCG steps on the order-1 level per V-cycle, >= 1 (20) */
+} pafem_mg_opts;
+
+/* Fill *opts with the defaults given in parentheses above. */
+void pafem_mg_default_opts(pafem_mg_opts* opts);
+/* Build the hierarchy for an operator assembled in FP64 whose coefficient is a
+ * constant or the built-in sin x one (INVALID_ARG for values at quadrature
+ * points): coarse spaces and operators, their quadrature data and diagonals,
+ * the transfer tables and the eigenvalue estimates (synchronous, on the
+ * legacy default stream).  opts may be NULL (defaults).  The hierarchy keeps
+ * a reference to `op`; results follow later re-assembly of `op` only through
+ * its quadrature data, not through the coarse levels. */
+int pafem_mg_create(pafem_op* op, const pafem_mg_opts* opts, pafem_mg** out);
+int pafem_mg_destroy(pafem_mg* mg);
+int pafem_mg_num_levels(const pafem_mg* mg);
+/* Order, dof count and lmax (0 on the order-1 level) of a level; any output may be NULL. */
+int pafem_mg_level_info(const pafem_mg* mg, int level, int* p, int64_t* ndofs, double* lmax);
+/* Replace the eigenvalue bound of a smoothed level (0 <= level < num_levels - 1). */
+int pafem_mg_set_lmax(pafem_mg* mg, int level, double lmax);
+/* uf = P uc from level + 1 to level (double vectors of the two levels' dof counts). */
+int pafem_mg_prolong(pafem_mg* mg, int level, const double* uc_dev, double* uf_dev, void* stream);
+/* rc = P^T rf from level to level + 1, essential coarse entries 0. */
+int pafem_mg_restrict(pafem_mg* mg, int level, const double* rf_dev, double* rc_dev, void* stream);
+/* x = the Chebyshev smoother applied to b from x = 0 on a smoothed level. */
+int pafem_mg_smooth(pafem_mg* mg, int level, const double* b_dev, double* x_dev, void* stream);
+/* z = one V-cycle applied to r on level 0 (r's essential entries should be 0). */
+int pafem_mg_vcycle(pafem_mg* mg, const double* r_dev, double* z_dev, void* stream);
+/* Solve A x = b (constrained operator of level 0) by flexible CG with one
+ * V-cycle per iteration; x holds the initial guess (essential entries equal
+ * to b's) and the solution.  opts->mode must be PAFEM_SOLVE_PLAIN_FP64; rtol
+ * and maxit as for pafem_solve_cg (convergence is confirmed on the FP64
+ * residual b - A x, restarting from x if needed; outer_iterations counts the
+ * restarts).  Synchronous.  NOT_CONVERGED if maxit is reached. */
+int pafem_mg_solve(pafem_mg* mg, const double* b_dev, double* x_dev, const pafem_solve_opts* opts,
+                   pafem_solve_stats* stats, void* stream);
+
 /* ---- reductions (exposed for testing the CG building blocks) --------------------- */
 /* Defined by: section "Kernel fusion" (dot products reduced with wavefront-
  * level instructions).

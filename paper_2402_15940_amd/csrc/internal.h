@@ -144,6 +144,19 @@ struct CgState {
   double rz_prev;  // r . z before the iteration that paused
 };
 
+// Device-resident scalars of the flexible CG of the p-multigrid solve.
+struct FcgState {
+  double rz;       // r . z
+  double pw;       // p . A p
+  double alpha, beta;
+  double rr;       // r . r
+  double rr_stop;  // converged when rr <= rr_stop
+  int iter;
+  int done;        // 1: converged on the recursive residual; 2: out of iterations
+  int maxit;
+  int pad;
+};
+
 struct Op : RefCounted {
   Space* space = nullptr;
   int kind = PAFEM_DIFFUSION;
@@ -440,8 +453,46 @@ hipError_t launch_axpy_from_f32(double* x, const double* norm2, const float* d32
 hipError_t launch_recip(const double* d, double* dinv64, float* dinv32, int64_t n,
                         hipStream_t s);
 
+// p-multigrid kernels (k_transfer.hip).  Orders pc = pf / 2; I1 is the
+// [pf+1][pc+1] interpolation table from the coarse to the fine GLL nodes.
+hipError_t launch_prolong(int pc, int pf, const double* uc, double* uf, int nx, int ny, int nz,
+                          const double* I1, int accumulate, const int* skip, hipStream_t s);
+// Per-element P^T of the fine values each element owns, into the coarse
+// x-interleaved E-vector (then summed per coarse node by launch_gather_xrows).
+hipError_t launch_restrict_elem(int pc, int pf, const double* rf, double* rcX, int nx, int ny,
+                                int nz, const double* I1, const int* skip, hipStream_t s);
+hipError_t launch_cheb_init(const double* b, const double* dinv, double* d, double* t, double c0,
+                            int64_t n, hipStream_t s);
+hipError_t launch_cheb_step(double* x, double* t, double* d, const double* w, const double* dinv,
+                            double c1, double c2, int first, int64_t n, hipStream_t s);
+hipError_t launch_fcg_update(double* x, double* r, const double* p, const double* w,
+                             const FcgState* st, int64_t n, double* part, int nb, hipStream_t s);
+hipError_t launch_fcg_dots(const double* z, const double* w, const double* r, int64_t n,
+                           double* part, int nb, hipStream_t s);
+hipError_t launch_fcg_init_dots(const double* r, const double* z, int64_t n, double* part, int nb,
+                                hipStream_t s);
+hipError_t launch_fcg_scalars(const double* part, int nb, int stage, FcgState* st, hipStream_t s);
+hipError_t launch_fcg_pupdate(double* p, const double* z, const FcgState* st, int64_t n,
+                              hipStream_t s);
+// Power iteration helpers: v = pseudo-random in [-1, 1) (counter-based hash
+// of the index); partials of (v . w, v . v / dinv, (dinv w) . (dinv w)); and
+// v = scale dinv w.
+hipError_t launch_hash_fill(double* v, int64_t n, uint64_t seed, hipStream_t s);
+hipError_t launch_power_dots(const double* v, const double* w, const double* dinv, int64_t n,
+                             double* part, int nb, hipStream_t s);
+hipError_t launch_power_next(double* v, const double* w, const double* dinv, double scale,
+                             int64_t n, hipStream_t s);
+
 // Solver helpers (solver.cpp).
 int ensure_dinv(Op* op, hipStream_t s, bool want32);
+// Exactly `iters` Jacobi-PCG steps (fewer only if the residual vanishes) on
+// the constrained FP64 operator from x = 0, with no host synchronization:
+// r holds the right-hand side on entry and is overwritten; p and Ap are work
+// vectors of length ndofs.
+int pcg_fixed(Op* op, double* r, double* x, double* p, double* Ap, int iters, hipStream_t s);
+// ||b - A x||_2 / ||b||_2 in FP64 (synchronous; Ax and r are scratch vectors).
+int relative_residual(Op* op, const double* b, const double* x, double* Ax, double* r,
+                      hipStream_t s, double& out);
 
 }  // namespace pafem
 

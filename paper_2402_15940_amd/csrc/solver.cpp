@@ -217,6 +217,54 @@ int true_residual(Op* op, const double* b, const double* x, double* Ax, double* 
 
 }  // namespace
 
+int pcg_fixed(Op* op, double* r, double* x, double* p, double* Ap, int iters, hipStream_t s) {
+  const int64_t n = op->space->ndofs;
+  const int nb = reduce_blocks(n);
+  PAFEM_TRY(ensure_dinv(op, s, false));
+  PAFEM_TRY(ensure_partials(op, n));
+  PAFEM_TRY(op->d_state.ensure(sizeof(CgState)));
+  double* part = op->d_part.as<double>();
+  CgState* st = op->d_state.as<CgState>();
+  const double* dinv = op->d_dinv64.as<double>();
+  PAFEM_TRY_HIP(launch_fill<double>(x, n, 0.0, nullptr, s));
+  PAFEM_TRY_HIP(launch_cg_init<double>(r, dinv, p, n, part, nb, s));
+  // rtol = 0: the state is done only when the residual vanishes or after iters steps
+  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, 1.0, 0.0, iters, st, s));
+  for (int k = 0; k < iters; ++k) {
+    if (fused_cg(op)) {
+      PAFEM_TRY((cg_step_fused<double, double>(op, x, r, p, dinv, part, st, s, 0)));
+    } else {
+      PAFEM_TRY(apply_impl<double>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, &st->done, s));
+      PAFEM_TRY_HIP(launch_dot_partial<double>(p, Ap, n, part, nb, &st->done, s));
+      PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
+      PAFEM_TRY_HIP((launch_cg_update<double, double>(x, r, p, Ap, dinv, n, part, nb, st, s)));
+      PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+    }
+    PAFEM_TRY_HIP(launch_cg_pupdate<double>(p, r, dinv, n, st, s));
+  }
+  return PAFEM_OK;
+}
+
+int relative_residual(Op* op, const double* b, const double* x, double* Ax, double* r,
+                      hipStream_t s, double& out) {
+  const int64_t n = op->space->ndofs;
+  const int nb = reduce_blocks(n);
+  PAFEM_TRY(ensure_partials(op, n));
+  double* part = op->d_part.as<double>();
+  double* dev = part + 2 * partial_pairs(n);
+  PAFEM_TRY_HIP(launch_dot_partial<double>(b, b, n, part, nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, dev + 1, s));
+  PAFEM_TRY(apply_impl<double>(op, x, Ax, PAFEM_APPLY_CONSTRAINED, nullptr, s));
+  PAFEM_TRY_HIP(launch_residual(b, Ax, r, n, s));
+  PAFEM_TRY_HIP(launch_dot_partial<double>(r, r, n, part, nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, dev, s));
+  double v[2] = {0.0, 0.0};
+  PAFEM_TRY_HIP(hipMemcpyAsync(v, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
+  out = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : std::sqrt(v[0]);
+  return PAFEM_OK;
+}
+
 int ensure_dinv(Op* op, hipStream_t s, bool want32) {
   Space* sp = op->space;
   const int64_t n = sp->ndofs;

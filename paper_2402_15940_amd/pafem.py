@@ -84,6 +84,11 @@ class ServerStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class MgOpts(C.Structure):
+    _fields_ = [("cheb_degree", C.c_int), ("cheb_lower", C.c_double), ("lmax_safety", C.c_double),
+                ("power_iters", C.c_int), ("coarse_iters", C.c_int)]
+
+
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 COEF_CONST, COEF_SINX = 0, 1
 
@@ -129,6 +134,18 @@ _SIGNATURES = {
     "pafem_rhs_assemble": (_I, [_P, _P, _P, _P]),
     "pafem_solve_cg": (_I, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveStats), _P]),
     "pafem_dot": (_I, [_P, _I64, _P, _P, _P, _P]),
+    "pafem_mg_default_opts": (None, [C.POINTER(MgOpts)]),
+    "pafem_mg_create": (_I, [_P, C.POINTER(MgOpts), _PP]),
+    "pafem_mg_destroy": (_I, [_P]),
+    "pafem_mg_num_levels": (_I, [_P]),
+    "pafem_mg_level_info": (_I, [_P, _I, C.POINTER(C.c_int), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_double)]),
+    "pafem_mg_set_lmax": (_I, [_P, _I, _D]),
+    "pafem_mg_prolong": (_I, [_P, _I, _P, _P, _P]),
+    "pafem_mg_restrict": (_I, [_P, _I, _P, _P, _P]),
+    "pafem_mg_smooth": (_I, [_P, _I, _P, _P, _P]),
+    "pafem_mg_vcycle": (_I, [_P, _P, _P, _P]),
+    "pafem_mg_solve": (_I, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveStats), _P]),
     "pafem_request_footprint": (_I64, [C.POINTER(Request)]),
     "pafem_server_create": (_I, [_P, _I64, _I, _I, _PP]),
     "pafem_server_submit": (_I, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
@@ -461,6 +478,101 @@ class Operator:
     def close(self):
         if getattr(self, "_h", None):
             lib().pafem_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _f64():
+    import torch
+    return torch.float64
+
+
+class Multigrid:
+    """p-multigrid hierarchy (orders p, p/2, ..., 1) of an FP64-assembled operator."""
+
+    def __init__(self, op: "Operator", cheb_degree=None, cheb_lower=None, lmax_safety=None,
+                 power_iters=None, coarse_iters=None):
+        o = MgOpts()
+        lib().pafem_mg_default_opts(C.byref(o))
+        for k, v in (("cheb_degree", cheb_degree), ("cheb_lower", cheb_lower),
+                     ("lmax_safety", lmax_safety), ("power_iters", power_iters),
+                     ("coarse_iters", coarse_iters)):
+            if v is not None:
+                setattr(o, k, v)
+        self.op = op
+        self.opts = o
+        h = C.c_void_p()
+        _check(lib().pafem_mg_create(op.handle, C.byref(o), C.byref(h)))
+        self._h = h
+
+    @property
+    def num_levels(self) -> int:
+        return lib().pafem_mg_num_levels(self._h)
+
+    def level_info(self, level: int) -> dict:
+        p, n, lm = C.c_int(), C.c_int64(), C.c_double()
+        _check(lib().pafem_mg_level_info(self._h, level, C.byref(p), C.byref(n), C.byref(lm)))
+        return {"p": p.value, "ndofs": n.value, "lmax": lm.value}
+
+    def set_lmax(self, level: int, lmax: float):
+        _check(lib().pafem_mg_set_lmax(self._h, level, float(lmax)))
+
+    def _vec(self, level):
+        import torch
+        return torch.empty(self.level_info(level)["ndofs"], dtype=torch.float64, device="cuda")
+
+    def prolong(self, level: int, uc, out=None, stream=None):
+        nf, nc = self.level_info(level)["ndofs"], self.level_info(level + 1)["ndofs"]
+        uf = self._vec(level) if out is None else out
+        _check(lib().pafem_mg_prolong(self._h, level, _dptr(uc, _f64(), nc, "uc"),
+                                      _dptr(uf, _f64(), nf, "uf"), _stream(stream)))
+        return uf
+
+    def restrict(self, level: int, rf, out=None, stream=None):
+        nf, nc = self.level_info(level)["ndofs"], self.level_info(level + 1)["ndofs"]
+        rc = self._vec(level + 1) if out is None else out
+        _check(lib().pafem_mg_restrict(self._h, level, _dptr(rf, _f64(), nf, "rf"),
+                                       _dptr(rc, _f64(), nc, "rc"), _stream(stream)))
+        return rc
+
+    def smooth(self, level: int, b, out=None, stream=None):
+        n = self.level_info(level)["ndofs"]
+        x = self._vec(level) if out is None else out
+        _check(lib().pafem_mg_smooth(self._h, level, _dptr(b, _f64(), n, "b"), _dptr(x, _f64(), n, "x"),
+                                     _stream(stream)))
+        return x
+
+    def vcycle(self, r, out=None, stream=None):
+        n = self.level_info(0)["ndofs"]
+        z = self._vec(0) if out is None else out
+        _check(lib().pafem_mg_vcycle(self._h, _dptr(r, _f64(), n, "r"), _dptr(z, _f64(), n, "z"),
+                                     _stream(stream)))
+        return z
+
+    def solve(self, b, x=None, rtol: float = 1e-10, maxit: int = 1000, stream=None):
+        """Flexible CG with one V-cycle per iteration; returns (x, stats dict)."""
+        import torch
+        n = self.level_info(0)["ndofs"]
+        if x is None:
+            x = torch.zeros_like(b)
+        o = SolveOpts(SOLVE_PLAIN_FP64, rtol, 0.0, maxit, 0, 1)
+        st = SolveStats()
+        rc = lib().pafem_mg_solve(self._h, _dptr(b, _f64(), n, "b"), _dptr(x, _f64(), n, "x"),
+                                  C.byref(o), C.byref(st), _stream(stream))
+        if rc not in (0, -4):
+            _check(rc)
+        d = st.as_dict()
+        d["converged"] = rc == 0
+        return x, d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pafem_mg_destroy(self._h)
             self._h = None
 
     def __del__(self):
