@@ -55,6 +55,16 @@ constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
 #endif
 constexpr int kNtQd[] = {PAFEM_NT_QD_BY_P};
 constexpr int kWavesDiff64[] = {PAFEM_WAVES_DIFF_F64};
+// the mass kernel's own tables, measured separately (8M dofs, p = 1..8):
+// elements per workgroup by q and the quadrature-data load type by p
+#ifndef PAFEM_NE_MASS_BY_Q
+#define PAFEM_NE_MASS_BY_Q 1, 1, 1, 7, 4, 8, 7, 5, 4, 3, 4
+#endif
+#ifndef PAFEM_NT_QD_MASS_BY_P
+#define PAFEM_NT_QD_MASS_BY_P 1, 1, 1, 0, 1, 1, 1, 1, 1
+#endif
+constexpr int kNeMassByQ[] = {PAFEM_NE_MASS_BY_Q};
+constexpr int kNtQdMass[] = {PAFEM_NT_QD_MASS_BY_P};
 // the same for the element pass that also forms the CG dot product
 #ifndef PAFEM_WAVES_DIFF_F64_DOT
 #define PAFEM_WAVES_DIFF_F64_DOT 1, 1, 1, 1, 3, 3, 1, 1, 1
@@ -143,7 +153,7 @@ struct Cfg {
   static constexpr int QQ = Q * Q;
   static constexpr int R = KIND == PAFEM_DIFFUSION ? odd_up(cmax(2 * N, 3 * Q)) : odd_up(cmax(N, Q));
   static constexpr int L = N * Q * R;  // LDS words per element
-  static constexpr int NE = kNeByQ[Q];
+  static constexpr int NE = KIND == PAFEM_DIFFUSION ? kNeByQ[Q] : kNeMassByQ[Q];
   static constexpr int THREADS = ((NE * QQ + 63) / 64) * 64;
   // waves per SIMD the register allocation must allow (occupancy floor)
   static constexpr int MIN_WAVES =
@@ -272,15 +282,122 @@ __device__ __forceinline__ void workgroup_dot(double* dot_part, double v, int64_
 }
 
 // ---------------------------------------------------------------------------
+// Fully matrix-free D along one stage-C line (qx, qy) of an element.  The
+// trilinear map is linear in each reference coordinate, so the Jacobian
+// column d x / d s does not depend on s (likewise for t and u): along the line
+// (s, t fixed) c1(u) = E0 + dE u, c2(u) = F0 + dF u and c3 is constant.  With
+// the adjugate rows r0 = c2 x c3, r1 = c3 x c1, r2 = c1 x c2 and
+// detJ = c1 . r0, diffusion needs w k (r_a . r_b) / detJ and mass w k detJ.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MfLine {
+  T E0[3], dE[3], F0[3], dF[3], C3[3];
+  T X0, dX, wxy;
+  __device__ __forceinline__ void init(const ApplyArgs<T>& a, int64_t e, int qx, int qy) {
+    const int64_t t1 = e / a.nx;
+    const int ex = (int)(e - t1 * a.nx), ey = (int)(t1 % a.ny), ez = (int)(t1 / a.ny);
+    const int64_t sy = a.nx + 1, sz = (int64_t)(a.nx + 1) * (a.ny + 1);
+    T v[2][2][2][3];  // [k (u)][j (t)][i (s)][coordinate]
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            v[k][j][i][d] = (T)a.verts[((ex + i) + (ey + j) * sy + (ez + k) * sz) * 3 + d];
+    const T s = (T)a.qpts[qx], t = (T)a.qpts[qy], s1 = T(1) - s, t1m = T(1) - t;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const T a0 = (v[0][0][1][d] - v[0][0][0][d]) * t1m + (v[0][1][1][d] - v[0][1][0][d]) * t;
+      const T a1 = (v[1][0][1][d] - v[1][0][0][d]) * t1m + (v[1][1][1][d] - v[1][1][0][d]) * t;
+      E0[d] = a0;
+      dE[d] = a1 - a0;
+      const T b0 = (v[0][1][0][d] - v[0][0][0][d]) * s1 + (v[0][1][1][d] - v[0][0][1][d]) * s;
+      const T b1 = (v[1][1][0][d] - v[1][0][0][d]) * s1 + (v[1][1][1][d] - v[1][0][1][d]) * s;
+      F0[d] = b0;
+      dF[d] = b1 - b0;
+      const T c00 = v[1][0][0][d] - v[0][0][0][d], c10 = v[1][0][1][d] - v[0][0][1][d];
+      const T c01 = v[1][1][0][d] - v[0][1][0][d], c11 = v[1][1][1][d] - v[0][1][1][d];
+      C3[d] = (c00 * s1 + c10 * s) * t1m + (c01 * s1 + c11 * s) * t;
+    }
+    const T f0 = (v[0][0][0][0] * s1 + v[0][0][1][0] * s) * t1m + (v[0][1][0][0] * s1 + v[0][1][1][0] * s) * t;
+    const T f1 = (v[1][0][0][0] * s1 + v[1][0][1][0] * s) * t1m + (v[1][1][0][0] * s1 + v[1][1][1][0] * s) * t;
+    X0 = f0;
+    dX = f1 - f0;
+    wxy = (T)(a.qwts[qx] * a.qwts[qy]);
+  }
+  // weight times coefficient, adjugate rows and detJ at point u = qpts[qz]
+  __device__ __forceinline__ void at(const ApplyArgs<T>& a, int qz, T& wk, T (&r)[3][3],
+                                     T& det) const {
+    const T u = (T)a.qpts[qz];
+    T c1[3], c2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      c1[d] = E0[d] + dE[d] * u;
+      c2[d] = F0[d] + dF[d] * u;
+    }
+    const T* c3 = C3;
+    r[0][0] = c2[1] * c3[2] - c2[2] * c3[1];
+    r[0][1] = c2[2] * c3[0] - c2[0] * c3[2];
+    r[0][2] = c2[0] * c3[1] - c2[1] * c3[0];
+    r[1][0] = c3[1] * c1[2] - c3[2] * c1[1];
+    r[1][1] = c3[2] * c1[0] - c3[0] * c1[2];
+    r[1][2] = c3[0] * c1[1] - c3[1] * c1[0];
+    r[2][0] = c1[1] * c2[2] - c1[2] * c2[1];
+    r[2][1] = c1[2] * c2[0] - c1[0] * c2[2];
+    r[2][2] = c1[0] * c2[1] - c1[1] * c2[0];
+    det = c1[0] * r[0][0] + c1[1] * r[0][1] + c1[2] * r[0][2];
+    T k = (T)a.coef_value;
+    if (a.coef_kind == COEF_SINX) k = T(1) + (T)a.coef_value * sin(T(2.0 * M_PI) * (X0 + dX * u));
+    wk = wxy * (T)a.qwts[qz] * k;
+  }
+};
+
+template <typename T, int Q>
+__device__ __forceinline__ void mf_fill_diffusion(const ApplyArgs<T>& a, int64_t e, int qx, int qy,
+                                                  T (&dq)[6][Q]) {
+  MfLine<T> L;
+  L.init(a, e, qx, qy);
+#pragma unroll
+  for (int qz = 0; qz < Q; ++qz) {
+    T wk, r[3][3], det;
+    L.at(a, qz, wk, r, det);
+    const T f = wk / det;
+    int m = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j)
+        dq[m++][qz] = f * (r[i][0] * r[j][0] + r[i][1] * r[j][1] + r[i][2] * r[j][2]);
+  }
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void mf_fill_mass(const ApplyArgs<T>& a, int64_t e, int qx, int qy,
+                                             T (&dq)[Q]) {
+  MfLine<T> L;
+  L.init(a, e, qx, qy);
+#pragma unroll
+  for (int qz = 0; qz < Q; ++qz) {
+    T wk, r[3][3], det;
+    L.at(a, qz, wk, r, det);
+    dq[qz] = wk * det;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // diffusion: y_e = sum_ij G_i^T S_ij G_j x_e, S = w k adj(J) adj(J)^T / detJ
 // stored as the 6 upper-triangle entries per quadrature point.
 // ---------------------------------------------------------------------------
 // Elements e0 .. e0+NE-1 (those below a.ne) with the workgroup's threads;
 // smem holds NE * L words.  Every thread of the workgroup must call it.
 // QD16: the quadrature data is stored in bfloat16 (a.qd16; FP32 arithmetic).
-template <int P, int Q, typename T, int SCATTER, int IDX, int NE, bool QD16 = false>
+template <int P, int Q, typename T, int SCATTER, int IDX, int NE, bool QD16 = false,
+          bool MF = false, bool DIR = false>
 __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0, T* smem,
-                                              int tid) {
+                                              int tid, T dir_beta = T(0)) {
   using C = Cfg<P, Q, T, PAFEM_DIFFUSION>;
   constexpr int N = C::N, QQ = C::QQ, L = C::L, R = C::R;
   constexpr int QQQ = Q * Q * Q;
@@ -311,13 +428,20 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
   Restrict<P, IDX, T> EA;
   EA.init(a, actA ? eA : 0);
 #pragma unroll
-  for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
+  for (int b = 0; b < N; ++b) {
+    const int32_t g = EA.dof(aA, b, cA);
+    // DIR: the CG direction formed on the fly, dinv r + beta p (a.x = p)
+    if constexpr (DIR)
+      u[b] = a.dir_dinv[g] * a.dir_r[g] + dir_beta * a.x[g];
+    else
+      u[b] = a.x[g];
+  }
   __builtin_amdgcn_sched_barrier(0);
 
   // Quadrature data of this thread's z-line: the dominant HBM stream, consumed
   // only in stage C, so it streams in while stages A and B run.
   T dq[6][Q];
-  {
+  if constexpr (!MF) {
     const int64_t off = (actC ? eC : 0) * (6 * QQQ) + qyC * Q + qxC;
     if constexpr (QD16) {  // BF16 storage, FP32 arithmetic
       const uint16_t* qd = a.qd16 + off;
@@ -397,6 +521,7 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
 
   // ---- stage C: z contraction, pointwise D, transposed z contraction ----
   if (actC) {
+    if constexpr (MF) mf_fill_diffusion<T, Q>(a, eC, qxC, qyC, dq);
     T* reg0 = smem + sC * L + qyC * R + qxC;  // + c*Q*R + k*Q
     T ibb[N], igb[N], ibg[N];
 #pragma unroll
@@ -545,9 +670,10 @@ __device__ __forceinline__ void diff_elements(const ApplyArgs<T>& a, int64_t e0,
 // ---------------------------------------------------------------------------
 // mass: y_e = B^T D B x_e with D = w rho detJ.
 // ---------------------------------------------------------------------------
-template <int P, int Q, typename T, int SCATTER, int IDX, int NE, bool QD16 = false>
+template <int P, int Q, typename T, int SCATTER, int IDX, int NE, bool QD16 = false,
+          bool MF = false, bool DIR = false>
 __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0, T* smem,
-                                              int tid) {
+                                              int tid, T dir_beta = T(0)) {
   using C = Cfg<P, Q, T, PAFEM_MASS>;
   constexpr int N = C::N, QQ = C::QQ, L = C::L, R = C::R;
   constexpr int QQQ = Q * Q * Q;
@@ -569,11 +695,18 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   Restrict<P, IDX, T> EA;
   EA.init(a, actA ? eA : 0);
 #pragma unroll
-  for (int b = 0; b < N; ++b) u[b] = a.x[EA.dof(aA, b, cA)];
+  for (int b = 0; b < N; ++b) {
+    const int32_t g = EA.dof(aA, b, cA);
+    // DIR: the CG direction formed on the fly, dinv r + beta p (a.x = p)
+    if constexpr (DIR)
+      u[b] = a.dir_dinv[g] * a.dir_r[g] + dir_beta * a.x[g];
+    else
+      u[b] = a.x[g];
+  }
   __builtin_amdgcn_sched_barrier(0);
 
   T dq[Q];
-  {
+  if constexpr (!MF) {
     const int64_t off = (actC ? eC : 0) * QQQ + qyC * Q + qxC;
     if constexpr (QD16) {
       const uint16_t* qd = a.qd16 + off;
@@ -582,7 +715,12 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
     } else {
       const T* qd = a.qd + off;
 #pragma unroll
-      for (int qz = 0; qz < Q; ++qz) dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
+      for (int qz = 0; qz < Q; ++qz) {
+        if constexpr (kNtQdMass[P] != 0)
+          dq[qz] = __builtin_nontemporal_load(qd + qz * QQ);
+        else
+          dq[qz] = qd[qz * QQ];
+      }
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -622,6 +760,7 @@ __device__ __forceinline__ void mass_elements(const ApplyArgs<T>& a, int64_t e0,
   __syncthreads();
 
   if (actC) {
+    if constexpr (MF) mf_fill_mass<T, Q>(a, eC, qxC, qyC, dq);
     T* reg0 = smem + sC * L + qyC * R + qxC;
     T in[N], ie[HN], io[LN], E[HN], O[HN];
 #pragma unroll

@@ -12,7 +12,7 @@ namespace {
 using apply::Cfg;
 using apply::xcd_block;
 
-template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16>
+template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16, bool MF = false>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
                              (SCATTER == kScatterXRowsDot
                                   ? Cfg<P, Q, T, PAFEM_DIFFUSION>::MIN_WAVES_DOT
@@ -23,10 +23,10 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_DIFFUSION>::THREADS),
   if (a.skip != nullptr && *a.skip) return;
   const int64_t nb = (a.ne + C::NE - 1) / C::NE;
   const int64_t e0 = xcd_block(blockIdx.x, nb) * C::NE;
-  apply::diff_elements<P, Q, T, SCATTER, IDX, C::NE, QD16>(a, e0, smem, threadIdx.x);
+  apply::diff_elements<P, Q, T, SCATTER, IDX, C::NE, QD16, MF>(a, e0, smem, threadIdx.x);
 }
 
-template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16>
+template <int P, int Q, typename T, int SCATTER, int IDX, bool QD16, bool MF = false>
 __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_mass(
     ApplyArgs<T> a) {
   using C = Cfg<P, Q, T, PAFEM_MASS>;
@@ -34,7 +34,7 @@ __global__ __launch_bounds__((Cfg<P, Q, T, PAFEM_MASS>::THREADS)) void k_apply_m
   if (a.skip != nullptr && *a.skip) return;
   const int64_t nb = (a.ne + C::NE - 1) / C::NE;
   const int64_t e0 = xcd_block(blockIdx.x, nb) * C::NE;
-  apply::mass_elements<P, Q, T, SCATTER, IDX, C::NE, QD16>(a, e0, smem, threadIdx.x);
+  apply::mass_elements<P, Q, T, SCATTER, IDX, C::NE, QD16, MF>(a, e0, smem, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -45,6 +45,16 @@ hipError_t launch_one(const ApplyArgs<T>& a, hipStream_t s) {
   constexpr int Q = P + 2;
   using C = Cfg<P, Q, T, KIND>;
   const int64_t nb = (a.ne + C::NE - 1) / C::NE;
+  // fully matrix-free form: lattice numbering, E-vector outputs only
+  if constexpr (IDX == PAFEM_INDEX_LATTICE && SCATTER != PAFEM_SCATTER_ATOMIC) {
+    if (a.mf) {
+      if (KIND == PAFEM_DIFFUSION)
+        hipLaunchKernelGGL((k_apply_diff<P, Q, T, SCATTER, IDX, false, true>), dim3(nb), dim3(C::THREADS), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_apply_mass<P, Q, T, SCATTER, IDX, false, true>), dim3(nb), dim3(C::THREADS), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   // bfloat16 quadrature data is a compile-time variant (FP32 arithmetic only),
   // so the FP64 and FP32 kernels carry no branch between their load streams
   if constexpr (std::is_same<T, float>::value) {
@@ -96,9 +106,15 @@ hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode
   // the stored maps must be on the device before a kernel may read them
   if (index_mode == PAFEM_INDEX_MAP && (a.E == nullptr || a.ess_mask == nullptr))
     return hipErrorInvalidValue;
-  if (a.x == nullptr || (a.qd == nullptr && a.qd16 == nullptr) || a.B == nullptr ||
-      a.G == nullptr)
+  if (a.mf) {
+    // recomputed geometry: lattice numbering and an E-vector output only
+    if (index_mode != PAFEM_INDEX_LATTICE || scatter_mode == PAFEM_SCATTER_ATOMIC ||
+        a.verts == nullptr || a.qpts == nullptr || a.qwts == nullptr || a.qd16 != nullptr)
+      return hipErrorInvalidValue;
+  } else if (a.qd == nullptr && a.qd16 == nullptr) {
     return hipErrorInvalidValue;
+  }
+  if (a.x == nullptr || a.B == nullptr || a.G == nullptr) return hipErrorInvalidValue;
   if (scatter_mode != PAFEM_SCATTER_ATOMIC && a.yE == nullptr) return hipErrorInvalidValue;
   if (scatter_mode == PAFEM_SCATTER_ATOMIC && a.y == nullptr) return hipErrorInvalidValue;
   switch (p) {

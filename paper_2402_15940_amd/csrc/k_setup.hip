@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kThreads) void k_qdata(GeomArgs g, int kind, int co
     k = 1.0 + coef_value * sin(2.0 * M_PI * X[0]);
   else
     k = coef_value;
+  if (qd64 == nullptr) return;  // Jacobian check only (matrix-free operators)
   if (kind == PAFEM_MASS) {
     const double d = w * k * det;
     qd64[e * qqq + qp] = d;
