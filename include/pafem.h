@@ -187,9 +187,32 @@ int pafem_op_set_coefficient_sinx(pafem_op* op, double amp);
 int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream);
 /* Device bytes the quadrature data occupies for prec_mask (or -1). */
 int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask);
+/* Device bytes the operator holds once assembled for prec_mask and used for
+ * applies and solves in those precisions: quadrature data, the E-vector
+ * workspace, the inverse diagonal (FP64, and FP32 when prec_mask asks for
+ * FP32 or BF16), the CG work vectors (three FP64, four FP32 for the
+ * mixed-precision modes, one FP64 copy of x for the graph launch form) and
+ * the reduction partials; the mesh vertices and the caller's vectors are not
+ * included (or -1). */
+int64_t pafem_op_footprint_bytes(const pafem_op* op, int prec_mask);
 /* Copy the stored quadrature data of precision `prec` into dst_dev
  * ([ne][C][q^3], C = 1 or 6, double or float). */
 int pafem_op_get_qdata(pafem_op* op, int prec, void* dst_dev, void* stream);
+/* Defined by: the assembly levels of section "State-of-the-art performance on
+ * exascale platforms and AMD GPUs" (fully matrix-free: everything the apply
+ * needs is computed on the fly; partial assembly: only the data at the
+ * quadrature points is stored).
+ * PAFEM_ASSEMBLY_PARTIAL (the default) stores D at pafem_op_assemble;
+ * PAFEM_ASSEMBLY_MATRIX_FREE stores nothing per quadrature point: every apply
+ * recomputes the geometric factors (and the coefficient) from the element
+ * corners, so its HBM stream is the vectors alone.  Matrix-free operators take
+ * a constant or the built-in sin x coefficient (INVALID_ARG at assembly for
+ * values at quadrature points), FP64 and FP32 (not BF16), and compute their
+ * diagonal from a temporary copy of D.  Takes effect at the next
+ * pafem_op_assemble (which then only checks the Jacobian sign). */
+#define PAFEM_ASSEMBLY_PARTIAL 0
+#define PAFEM_ASSEMBLY_MATRIX_FREE 1
+int pafem_op_set_assembly_level(pafem_op* op, int level);
 /* Choose how E^T sums element contributions (default DETERMINISTIC). */
 int pafem_op_set_scatter_mode(pafem_op* op, int mode);
 /* Choose where the kernels take E (and, in deterministic mode, E^T) from:
@@ -259,7 +282,21 @@ typedef struct {
   int maxit;         /* plain, MIXED: max CG iterations; IR: max inner iterations per solve */
   int max_outer;     /* IR: max refinement steps (MIXED: unused) */
   int check_every;   /* host reads the residual every this many iterations (>= 1) */
+  int launch;        /* PAFEM_LAUNCH_*: how the iterations between two reads are issued */
 } pafem_solve_opts;
+
+/* Launch forms of the CG iterations (the same arithmetic; kernels and graph
+ * give bitwise equal results, the persistent kernel sums its reductions in
+ * another fixed order).  The fully fused form follows the paper's section on
+ * kernel fusion. */
+#define PAFEM_LAUNCH_KERNELS 0    /* one launch per kernel of every iteration */
+#define PAFEM_LAUNCH_GRAPH 1      /* the check_every iterations captured once in a HIP graph
+                                     (kept by the operator and reused while the vectors are
+                                     the same) and replayed; PLAIN_FP64 and the IR inner solves */
+#define PAFEM_LAUNCH_PERSISTENT 2 /* check_every whole iterations in one cooperative persistent
+                                     kernel with grid-wide barriers (bounded waits); PLAIN_FP64
+                                     with the deterministic E^T on the lattice numbering, partial
+                                     assembly level */
 
 typedef struct {
   int iterations;       /* plain, MIXED: CG iterations; IR: total inner iterations */

@@ -64,6 +64,7 @@ hipError_t upload_basis_tables() {
   std::vector<float> t32(t64.begin(), t64.end());
   hipError_t e = upload_tables_apply(t64.data(), t32.data(), t64.size());
   if (e == hipSuccess) e = upload_tables_batched(t64.data(), t32.data(), t64.size());
+  if (e == hipSuccess) e = upload_tables_persistent(t64.data(), t32.data(), t64.size());
   return e;
 }
 
@@ -187,6 +188,16 @@ ApplyArgs<T> make_args(Op* op, const T* x, T* y, T* yE, int flags, const int* sk
   a.constrained = (flags & PAFEM_APPLY_CONSTRAINED) ? 1 : 0;
   a.accumulate = (flags & PAFEM_APPLY_ACCUMULATE) ? 1 : 0;
   a.skip = skip;
+  if (op->level == PAFEM_ASSEMBLY_MATRIX_FREE) {
+    a.mf = 1;
+    a.qd = nullptr;
+    a.qd16 = nullptr;
+    a.coef_kind = op->coef_kind;
+    a.coef_value = op->coef_value;
+    a.verts = sp->mesh->d_verts.as<double>();
+    a.qpts = tabPts(op->d_tab64, op->q, n);
+    a.qwts = tabWts(op->d_tab64, op->q, n);
+  }
   return a;
 }
 
@@ -208,7 +219,11 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
   if (im == PAFEM_INDEX_MAP) PAFEM_TRY(ensure_device_maps(sp));
   if (op->scatter_mode == PAFEM_SCATTER_ATOMIC && (flags & PAFEM_APPLY_CONSTRAINED))
     PAFEM_TRY(ensure_ess(sp, true));
-  if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC) {
+  if (op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC || op->level == PAFEM_ASSEMBLY_MATRIX_FREE) {
+    if (op->level == PAFEM_ASSEMBLY_MATRIX_FREE) {
+      PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
+      return apply_impl<T>(op, x, y, flags, skip, s, qprec, op->d_evec.ptr);
+    }
     PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
     if (im == PAFEM_INDEX_LATTICE)
       return apply_impl<T>(op, x, y, flags, skip, s, qprec, op->d_evec.ptr);
@@ -254,6 +269,22 @@ int apply_elements_dot(Op* op, const T* p, const int* skip, hipStream_t s, int q
   return PAFEM_OK;
 }
 template int apply_elements_dot<double>(Op*, const double*, const int*, hipStream_t, int, int*);
+
+int cg_element_args(Op* op, const double* p, ApplyArgs<double>* out, int64_t* groups) {
+  Space* sp = op->space;
+  const int64_t nb = element_blocks(op->kind, sp->p, sp->ne, false);
+  if (nb <= 0 || nb > INT32_MAX) {
+    set_error("internal: element workgroup count out of range");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, sp->p + 1) * sizeof(double)));
+  PAFEM_TRY(op->d_gpart.ensure((size_t)nb * sizeof(double)));
+  *out = make_args<double>(op, p, nullptr, op->d_evec.as<double>(), PAFEM_APPLY_CONSTRAINED,
+                           nullptr);
+  out->dot_part = op->d_gpart.as<double>();
+  *groups = nb;
+  return PAFEM_OK;
+}
 template int apply_elements_dot<float>(Op*, const float*, const int*, hipStream_t, int, int*);
 
 // y = E^T yE over every node (constrained: essential rows set to 0), in the
@@ -280,10 +311,22 @@ int diagonal_impl(Op* op, double* d, int constrained, hipStream_t s) {
   Space* sp = op->space;
   const int n = sp->p + 1;
   PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, n) * sizeof(double)));
-  PAFEM_TRY_HIP(launch_diag_elem(op->kind, sp->p, op->q, op->d_qd64.as<double>(),
-                                 tabB<double>(op->d_tab64), tabG<double>(op->d_tab64, op->q, n),
-                                 sp->ne, op->d_evec.as<double>(), s));
-  return gather_full(op, op->d_evec.as<double>(), 0, d, s);
+  const double* qd = op->d_qd64.as<double>();
+  DevBuf tmp;  // matrix-free: D computed for the diagonal only, then released
+  if (op->level == PAFEM_ASSEMBLY_MATRIX_FREE) {
+    const size_t nq = (size_t)sp->ne * op->q * op->q * op->q * op->ncomp;
+    PAFEM_TRY(tmp.ensure(nq * sizeof(double)));
+    GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, n), tabWts(op->d_tab64, op->q, n));
+    PAFEM_TRY_HIP(launch_qdata(g, op->kind, op->coef_kind, op->coef_value, nullptr,
+                               tmp.as<double>(), nullptr, nullptr, op->d_flag.as<int>(), s));
+    qd = tmp.as<double>();
+  }
+  PAFEM_TRY_HIP(launch_diag_elem(op->kind, sp->p, op->q, qd, tabB<double>(op->d_tab64),
+                                 tabG<double>(op->d_tab64, op->q, n), sp->ne,
+                                 op->d_evec.as<double>(), s));
+  PAFEM_TRY(gather_full(op, op->d_evec.as<double>(), 0, d, s));
+  if (tmp.ptr) PAFEM_TRY_HIP(hipStreamSynchronize(s));  // before the temporary is freed
+  return PAFEM_OK;
 }
 
 template int apply_impl<double>(Op*, const double*, double*, int, const int*, hipStream_t, int,
@@ -585,10 +628,26 @@ int pafem_op_set_coefficient_sinx(pafem_op* op, double amp) {
 
 int64_t pafem_op_qdata_bytes(const pafem_op* op, int prec_mask) {
   if (!op) return -1;
+  if (op->level == PAFEM_ASSEMBLY_MATRIX_FREE) return 0;
   const int64_t n = op->space->ne * (int64_t)op->q * op->q * op->q * op->ncomp;
   int64_t b = n * 8;
   if (prec_mask & PAFEM_FP32) b += n * 4;
   if (prec_mask & PAFEM_BF16) b += n * 2;
+  return b;
+}
+
+int64_t pafem_op_footprint_bytes(const pafem_op* op, int prec_mask) {
+  if (!op || (prec_mask & ~(PAFEM_FP64 | PAFEM_FP32 | PAFEM_BF16)) != 0) return -1;
+  const Space* sp = op->space;
+  const int64_t n = sp->ndofs;
+  const bool f32 = (prec_mask & (PAFEM_FP32 | PAFEM_BF16)) != 0;
+  int64_t b = pafem_op_qdata_bytes(op, prec_mask | PAFEM_FP64);
+  b += evec_words(sp->ne, sp->p + 1) * 8;        // E-vector workspace
+  b += n * (8 + (f32 ? 4 : 0));                   // inverse diagonal
+  b += n * (3 * 8 + 8) + (f32 ? n * 4 * 4 : 0);   // CG vectors (+ x for the graph form)
+  const int64_t nb = reduce_blocks(n);
+  b += ((nb > kMaxCgParts ? nb : kMaxCgParts) * 2 + 8) * 8;  // reduction partials
+  b += element_blocks(op->kind, sp->p, sp->ne, false) * 8;  // element-pass partials
   return b;
 }
 
@@ -597,10 +656,17 @@ int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
   CHECK_ARG(op, "NULL argument");
   CHECK_ARG((prec_mask & ~(PAFEM_FP64 | PAFEM_FP32 | PAFEM_BF16)) == 0, "unknown precision bits");
   PAFEM_TRY(need_device(op->space->mesh->ctx));
+  const bool mf = op->level == PAFEM_ASSEMBLY_MATRIX_FREE;
+  if (mf) {
+    CHECK_ARG((prec_mask & PAFEM_BF16) == 0,
+              "a matrix-free operator stores no quadrature data to round to bfloat16");
+    CHECK_ARG(op->coef_kind != COEF_QPTS,
+              "a matrix-free operator needs a constant or the built-in coefficient");
+  }
   const size_t n = (size_t)op->space->ne * op->q * op->q * op->q * op->ncomp;
-  PAFEM_TRY(op->d_qd64.ensure(n * sizeof(double)));
+  if (!mf) PAFEM_TRY(op->d_qd64.ensure(n * sizeof(double)));
   float* q32 = nullptr;
-  if (prec_mask & PAFEM_FP32) {
+  if ((prec_mask & PAFEM_FP32) && !mf) {
     PAFEM_TRY(op->d_qd32.ensure(n * sizeof(float)));
     q32 = op->d_qd32.as<float>();
   }
@@ -613,13 +679,15 @@ int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
   GeomArgs g = geom(op, tabPts(op->d_tab64, op->q, nn), tabWts(op->d_tab64, op->q, nn));
   hipStream_t s = S(stream);
   PAFEM_TRY_HIP(hipMemsetAsync(op->d_flag.ptr, 0, sizeof(int), s));
+  // (matrix-free: the same pass with nothing stored checks the Jacobian sign)
   PAFEM_TRY_HIP(launch_qdata(g, op->kind, op->coef_kind, op->coef_value, op->d_coef.as<double>(),
-                             op->d_qd64.as<double>(), q32, q16, op->d_flag.as<int>(), s));
+                             mf ? nullptr : op->d_qd64.as<double>(), q32, q16,
+                             op->d_flag.as<int>(), s));
   int flag = 0;
   PAFEM_TRY_HIP(hipMemcpyAsync(&flag, op->d_flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
   PAFEM_TRY_HIP(hipStreamSynchronize(s));
   op->have64 = true;
-  op->have32 = q32 != nullptr;
+  op->have32 = mf ? (prec_mask & PAFEM_FP32) != 0 : q32 != nullptr;
   op->have16 = q16 != nullptr;
   op->have_dinv = false;
   if (flag) {
@@ -633,6 +701,7 @@ int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
 int pafem_op_get_qdata(pafem_op* op, int prec, void* dst, void* stream) {
   clear_error();
   CHECK_ARG(op && dst, "NULL argument");
+  CHECK_ARG(op->level == PAFEM_ASSEMBLY_PARTIAL, "a matrix-free operator stores no quadrature data");
   CHECK_ARG(prec == PAFEM_FP64 || prec == PAFEM_FP32 || prec == PAFEM_BF16,
             "prec must be FP64, FP32 or BF16");
   const bool have = prec == PAFEM_FP64 ? op->have64 : prec == PAFEM_FP32 ? op->have32 : op->have16;
@@ -645,11 +714,34 @@ int pafem_op_get_qdata(pafem_op* op, int prec, void* dst, void* stream) {
   return PAFEM_OK;
 }
 
+int pafem_op_set_assembly_level(pafem_op* op, int level) {
+  clear_error();
+  CHECK_ARG(op, "NULL argument");
+  CHECK_ARG(level == PAFEM_ASSEMBLY_PARTIAL || level == PAFEM_ASSEMBLY_MATRIX_FREE,
+            "unknown assembly level");
+  if (level == PAFEM_ASSEMBLY_MATRIX_FREE) {
+    CHECK_ARG(op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC &&
+                  op->index_mode == PAFEM_INDEX_LATTICE,
+              "the matrix-free level runs the deterministic E^T on the lattice numbering");
+  }
+  if (level != op->level) {
+    op->level = level;
+    op->have64 = op->have32 = op->have16 = false;
+    op->have_dinv = false;
+    op->d_qd64.release();
+    op->d_qd32.release();
+    op->d_qd16.release();
+  }
+  return PAFEM_OK;
+}
+
 int pafem_op_set_scatter_mode(pafem_op* op, int mode) {
   clear_error();
   CHECK_ARG(op, "NULL argument");
   CHECK_ARG(mode == PAFEM_SCATTER_ATOMIC || mode == PAFEM_SCATTER_DETERMINISTIC,
             "unknown scatter mode");
+  CHECK_ARG(op->level == PAFEM_ASSEMBLY_PARTIAL || mode == PAFEM_SCATTER_DETERMINISTIC,
+            "the matrix-free level runs the deterministic E^T");
   op->scatter_mode = mode;
   return PAFEM_OK;
 }
@@ -658,6 +750,8 @@ int pafem_op_set_restriction_mode(pafem_op* op, int mode) {
   clear_error();
   CHECK_ARG(op, "NULL argument");
   CHECK_ARG(mode == PAFEM_INDEX_LATTICE || mode == PAFEM_INDEX_MAP, "unknown restriction mode");
+  CHECK_ARG(op->level == PAFEM_ASSEMBLY_PARTIAL || mode == PAFEM_INDEX_LATTICE,
+            "the matrix-free level runs on the lattice numbering");
   op->index_mode = mode;
   return PAFEM_OK;
 }

@@ -160,6 +160,7 @@ struct FcgState {
 struct Op : RefCounted {
   Space* space = nullptr;
   int kind = PAFEM_DIFFUSION;
+  int level = PAFEM_ASSEMBLY_PARTIAL;  // or PAFEM_ASSEMBLY_MATRIX_FREE
   int q = 0;
   int ncomp = 6;
   int coef_kind = COEF_CONST;
@@ -179,6 +180,17 @@ struct Op : RefCounted {
   DevBuf d_state;               // CgState
   DevBuf d_dinv64, d_dinv32;
   bool have_dinv = false;
+  // captured CG iterations (PAFEM_LAUNCH_GRAPH): the graph, the stream it was
+  // captured on and what it was captured for
+  hipGraphExec_t cg_graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  const void* cg_graph_key[10] = {};
+  // persistent CG (PAFEM_LAUNCH_PERSISTENT): workgroup partials, barrier, error flag
+  DevBuf d_pers;
+  ~Op() {
+    if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 // Shared host helpers (api.cpp).
@@ -232,6 +244,18 @@ struct ApplyArgs {
   int accumulate;     // atomic mode: y holds a previous result to add to
   const int* skip;    // if non-null and *skip != 0, the kernel does nothing
   double* dot_part;   // if non-null: per workgroup, sum over its elements of x_e . y_e
+  // fully matrix-free form (mf != 0): D recomputed at every quadrature point
+  // from the corner vertices instead of read from qd
+  int mf;
+  int coef_kind;      // COEF_CONST or COEF_SINX
+  double coef_value;
+  const double* verts;  // [(nx+1)(ny+1)(nz+1)][3]
+  const double* qpts;   // [q] Gauss points on [0,1]
+  const double* qwts;   // [q] their weights
+  // element pass on a CG direction formed on the fly (persistent CG):
+  // the input is dir_dinv .* dir_r + beta x
+  const T* dir_r;
+  const T* dir_dinv;
 };
 
 // Tables of the element kernels for order p (n = p+1 nodes, q = p+2 points):
@@ -381,6 +405,9 @@ hipError_t launch_cg_alpha_wide(const double* partials, int nb, CgState* st, hip
 template <typename T>
 int apply_elements_dot(Op* op, const T* p, const int* skip, hipStream_t s, int qprec,
                        int* nparts);
+// Argument block of the FP64 CG element pass of A p (constrained, x-interleaved
+// E-vector, one partial of p . A p per element group) and the group count.
+int cg_element_args(Op* op, const double* p, ApplyArgs<double>* out, int64_t* groups);
 // Workgroups of the element pass of `kind`, order p, over ne elements.
 int64_t element_blocks(int kind, int p, int64_t ne, bool f32);
 
@@ -482,6 +509,15 @@ hipError_t launch_power_dots(const double* v, const double* w, const double* din
                              double* part, int nb, hipStream_t s);
 hipError_t launch_power_next(double* v, const double* w, const double* dinv, double scale,
                              int64_t n, hipStream_t s);
+
+// Up to `iters` FP64 Jacobi-PCG iterations in one cooperative persistent
+// launch (k_persistent.hip); *grid receives the workgroup count (<= max_blocks).
+hipError_t launch_pcg_persistent(int kind, int p, const ApplyArgs<double>& a, int64_t groups,
+                                 double* xs, double* r, const double* dinv, double* bpart,
+                                 double* npart, CgState* st, void* bar, int* err,
+                                 long long spin_limit, int iters, int max_blocks, int* grid,
+                                 hipStream_t s);
+hipError_t upload_tables_persistent(const double* t64, const float* t32, size_t words);
 
 // Solver helpers (solver.cpp).
 int ensure_dinv(Op* op, hipStream_t s, bool want32);

@@ -64,10 +64,87 @@ int cg_step_fused(Op* op, TX* x, T* r, const T* p, const T* dinv, double* part, 
 
 // Solve A x = rhs for the constrained operator in precision T.  On entry x is
 // the initial guess unless x0_zero.  r, p, Ap are work vectors of length n.
+// The check_every iterations of one CG loop pass (the separate-kernel or the
+// fused step, then the direction update), enqueued on s.
+template <typename T>
+int enqueue_iterations(Op* op, T* x, T* r, T* p, T* Ap, const T* dinv, double* part,
+                       CgState* st, int check_every, hipStream_t s, int qprec) {
+  const int64_t n = op->space->ndofs;
+  const int nb = reduce_blocks(n);
+  const int* done = &st->done;
+  for (int k = 0; k < check_every; ++k) {
+    if (fused_cg(op)) {
+      PAFEM_TRY((cg_step_fused<T, T>(op, x, r, p, dinv, part, st, s, qprec)));
+    } else {
+      PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
+      PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
+      PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
+      PAFEM_TRY_HIP((launch_cg_update<T, T>(x, r, p, Ap, dinv, n, part, nb, st, s)));
+      PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+    }
+    PAFEM_TRY_HIP(launch_cg_pupdate<T>(p, r, dinv, n, st, s));
+  }
+  return PAFEM_OK;
+}
+
+// The op's captured graph of check_every iterations for these vectors,
+// captured now unless the cached one was captured for the same ones.  Every
+// buffer the kernels touch is allocated before the capture.
+template <typename T>
+int cg_graph(Op* op, T* x, T* r, T* p, T* Ap, const T* dinv, double* part, CgState* st,
+             int check_every, int qprec, hipGraphExec_t* out) {
+  const void* key[10] = {x, r, p, Ap, dinv, part, st, (const void*)(intptr_t)check_every,
+                         (const void*)(intptr_t)qprec, (const void*)(intptr_t)sizeof(T)};
+  bool same = op->cg_graph != nullptr;
+  for (int i = 0; i < 10 && same; ++i) same = op->cg_graph_key[i] == key[i];
+  if (same) {
+    *out = op->cg_graph;
+    return PAFEM_OK;
+  }
+  if (op->cg_graph) {
+    PAFEM_TRY_HIP(hipGraphExecDestroy(op->cg_graph));
+    op->cg_graph = nullptr;
+  }
+  Space* sp = op->space;
+  PAFEM_TRY(op->d_evec.ensure((size_t)evec_words(sp->ne, sp->p + 1) * sizeof(double)));
+  if (fused_cg(op)) {
+    PAFEM_TRY(op->d_gpart.ensure(
+        (size_t)element_blocks(op->kind, sp->p, sp->ne, !std::is_same<T, double>::value) *
+        sizeof(double)));
+  } else {
+    if (op->index_mode == PAFEM_INDEX_MAP) PAFEM_TRY(ensure_device_maps(sp));
+    if (op->scatter_mode == PAFEM_SCATTER_ATOMIC) PAFEM_TRY(ensure_ess(sp, true));
+  }
+  if (!op->cap_stream)
+    PAFEM_TRY_HIP(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = op->cap_stream;
+  PAFEM_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  const int rc = enqueue_iterations<T>(op, x, r, p, Ap, dinv, part, st, check_every, cs, qprec);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  if (rc != PAFEM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  PAFEM_TRY_HIP(ec);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  PAFEM_TRY_HIP(ei);
+  op->cg_graph = exec;
+  for (int i = 0; i < 10; ++i) op->cg_graph_key[i] = key[i];
+  *out = exec;
+  return PAFEM_OK;
+}
+
+// Spin limit of the persistent kernel's barrier waits (each poll sleeps
+// briefly): far beyond any legitimate wait, so that a stall ends the launch.
+constexpr long long kSpinLimit = 1LL << 24;
+
 template <typename T>
 int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T* dinv,
             double rtol, int maxit, int check_every, hipStream_t s, CgResult& res,
-            int qprec = 0) {
+            int qprec = 0, int launch = PAFEM_LAUNCH_KERNELS) {
   Space* sp = op->space;
   const int64_t n = sp->ndofs;
   const int nb = reduce_blocks(n);
@@ -102,24 +179,54 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
   PAFEM_TRY_HIP(launch_cg_init<T>(r, dinv, p, n, part, nb, s));
   PAFEM_TRY_HIP(launch_cg_init_final(part, nb, bb, rtol, maxit, st, s));
 
-  const int* done = &st->done;
   CgState hs{};
-  for (;;) {
-    for (int k = 0; k < check_every; ++k) {
-      if (fused_cg(op)) {
-        PAFEM_TRY((cg_step_fused<T, T>(op, x, r, p, dinv, part, st, s, qprec)));
-      } else {
-        PAFEM_TRY(apply_impl<T>(op, p, Ap, PAFEM_APPLY_CONSTRAINED, done, s, qprec));
-        PAFEM_TRY_HIP(launch_dot_partial<T>(p, Ap, n, part, nb, done, s));
-        PAFEM_TRY_HIP(launch_cg_alpha(part, nb, st, s));
-        PAFEM_TRY_HIP((launch_cg_update<T, T>(x, r, p, Ap, dinv, n, part, nb, st, s)));
-        PAFEM_TRY_HIP(launch_cg_beta(part, nb, st, s));
+  if (launch == PAFEM_LAUNCH_PERSISTENT) {
+    if constexpr (std::is_same<T, double>::value) {
+      ApplyArgs<double> a{};
+      int64_t groups = 0;
+      PAFEM_TRY(cg_element_args(op, p, &a, &groups));
+      constexpr int kMaxPersistentBlocks = 8192;
+      PAFEM_TRY(op->d_pers.ensure((3 * (size_t)kMaxPersistentBlocks + 16) * sizeof(double)));
+      double* bpart = op->d_pers.as<double>();
+      double* npart = bpart + kMaxPersistentBlocks;
+      void* bar = npart + 2 * kMaxPersistentBlocks;
+      int* err = reinterpret_cast<int*>(static_cast<double*>(bar) + 1);
+      PAFEM_TRY_HIP(hipMemsetAsync(bar, 0, 2 * sizeof(double), s));
+      for (;;) {
+        int grid = 0;
+        PAFEM_TRY_HIP(launch_pcg_persistent(op->kind, sp->p, a, groups, x, r, dinv, bpart, npart,
+                                            st, bar, err, kSpinLimit, check_every,
+                                            kMaxPersistentBlocks, &grid, s));
+        int herr = 0;
+        PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        PAFEM_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        PAFEM_TRY_HIP(hipStreamSynchronize(s));
+        if (herr) {
+          set_error("persistent CG: a grid barrier wait exceeded its bound");
+          return PAFEM_ERR_HIP;
+        }
+        if (hs.done) break;
       }
-      PAFEM_TRY_HIP(launch_cg_pupdate<T>(p, r, dinv, n, st, s));
+    } else {
+      set_error("internal: the persistent CG runs in FP64");
+      return PAFEM_ERR_INVALID_ARG;
     }
-    PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    PAFEM_TRY_HIP(hipStreamSynchronize(s));
-    if (hs.done) break;
+  } else if (launch == PAFEM_LAUNCH_GRAPH) {
+    hipGraphExec_t g = nullptr;
+    PAFEM_TRY((cg_graph<T>(op, x, r, p, Ap, dinv, part, st, check_every, qprec, &g)));
+    for (;;) {
+      PAFEM_TRY_HIP(hipGraphLaunch(g, s));
+      PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      PAFEM_TRY_HIP(hipStreamSynchronize(s));
+      if (hs.done) break;
+    }
+  } else {
+    for (;;) {
+      PAFEM_TRY((enqueue_iterations<T>(op, x, r, p, Ap, dinv, part, st, check_every, s, qprec)));
+      PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      PAFEM_TRY_HIP(hipStreamSynchronize(s));
+      if (hs.done) break;
+    }
   }
   res.iterations = hs.iter;
   res.rr = hs.rr;
@@ -304,6 +411,19 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     return PAFEM_ERR_INVALID_ARG;
   }
   const bool mixed = o->mode == PAFEM_SOLVE_MIXED_FP32 || o->mode == PAFEM_SOLVE_MIXED_BF16;
+  if (o->launch < PAFEM_LAUNCH_KERNELS || o->launch > PAFEM_LAUNCH_PERSISTENT) {
+    set_error("unknown launch form");
+    return PAFEM_ERR_INVALID_ARG;
+  }
+  if ((mixed && o->launch != PAFEM_LAUNCH_KERNELS) ||
+      (o->launch == PAFEM_LAUNCH_PERSISTENT &&
+       (o->mode != PAFEM_SOLVE_PLAIN_FP64 || !fused_cg(op) ||
+        op->level != PAFEM_ASSEMBLY_PARTIAL))) {
+    set_error("launch form not available for this mode (graph: PLAIN_FP64 and IR; persistent: "
+              "PLAIN_FP64 with the deterministic E^T on the lattice numbering and stored "
+              "quadrature data)");
+    return PAFEM_ERR_INVALID_ARG;
+  }
   if (mixed && !(o->inner_rtol > 0.0 && o->inner_rtol < 1.0)) {
     set_error("MIXED modes need inner_rtol (the replacement factor) in (0, 1)");
     return PAFEM_ERR_INVALID_ARG;
@@ -326,12 +446,14 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
   *stats = pafem_solve_stats{};
 
   PAFEM_TRY(ensure_dinv(op, s, ir));
-  // workspace: 3 FP64 vectors, plus 4 FP32 vectors for IR
+  // workspace: 3 FP64 vectors, plus 4 FP32 vectors for IR, plus the solution
+  // for the graph form (so that the captured iterations outlive one call)
   const size_t need = 3 * n * sizeof(double) + (ir ? 4 * n * sizeof(float) : 0);
-  PAFEM_TRY(op->d_cg.ensure(need));
+  PAFEM_TRY(op->d_cg.ensure(need + n * sizeof(double)));
   double* r = op->d_cg.as<double>();
   double* p = r + n;
   double* Ap = p + n;
+  double* x_graph = reinterpret_cast<double*>(reinterpret_cast<char*>(op->d_cg.ptr) + need);
 
   int rc = PAFEM_OK;
   if (mixed) {
@@ -357,13 +479,18 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     int total = 0, restarts = 0;
     bool ok = false;
     double rel = 0.0, true_rel = 0.0;
+    double* xs = x;
+    if (o->launch == PAFEM_LAUNCH_GRAPH) {
+      xs = x_graph;
+      PAFEM_TRY_HIP(hipMemcpyAsync(xs, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     for (;;) {
       CgResult res;
-      PAFEM_TRY(run_pcg<double>(op, b, x, false, r, p, Ap, op->d_dinv64.as<double>(), o->rtol,
-                                o->maxit - total, o->check_every, s, res));
+      PAFEM_TRY(run_pcg<double>(op, b, xs, false, r, p, Ap, op->d_dinv64.as<double>(), o->rtol,
+                                o->maxit - total, o->check_every, s, res, 0, o->launch));
       total += res.iterations;
       rel = res.bb > 0 ? std::sqrt(res.rr / res.bb) : 0.0;
-      PAFEM_TRY(true_residual(op, b, x, Ap, r, res.bb, s, true_rel));
+      PAFEM_TRY(true_residual(op, b, xs, Ap, r, res.bb, s, true_rel));
       if (true_rel <= o->rtol) {
         ok = true;
         break;
@@ -371,6 +498,8 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
       if (!res.converged || total >= o->maxit || res.iterations == 0) break;
       ++restarts;
     }
+    if (xs != x)
+      PAFEM_TRY_HIP(hipMemcpyAsync(x, xs, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     stats->iterations = total;
     stats->outer_iterations = restarts;
     stats->rel_res = rel;
@@ -416,7 +545,8 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
       PAFEM_TRY(run_pcg<float>(op, r32, d32, true, r32, p32, Ap32, op->d_dinv32.as<float>(),
                                o->inner_rtol > 0 ? o->inner_rtol : 1e-4, o->maxit,
                                o->check_every, s, res,
-                               o->mode == PAFEM_SOLVE_IR_BF16 ? PAFEM_BF16 : PAFEM_FP32));
+                               o->mode == PAFEM_SOLVE_IR_BF16 ? PAFEM_BF16 : PAFEM_FP32,
+                               o->launch));
       total_inner += res.iterations;
       PAFEM_TRY_HIP(launch_axpy_from_f32(x, rr_dev, d32, n, s));
       PAFEM_TRY(apply_impl<double>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));

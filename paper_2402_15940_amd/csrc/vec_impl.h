@@ -149,5 +149,117 @@ __device__ __forceinline__ void gather_lattice_node(const T* __restrict__ yE, in
                                    ii - r * Lx, r % Ly, r / Ly);
 }
 
+// E^T from the x-interleaved E-vector, one thread per kXRowsNodes nodes:
+// workgroup b takes the kXRowsNodes * kThreads consecutive lattice nodes from
+// b kXRowsNodes kThreads on (lane t: nodes base + q kThreads + t), so every
+// lane is busy and a wavefront may span the end of a lattice row.  Node
+// I = ex p + a of row (J, K) reads word ex w + a of each (y, z) candidate's
+// run (neighbouring lanes: neighbouring words) and, on an x face (a = 0,
+// ex > 0), also the word of element ex-1's local p.  All loads of a thread
+// are issued before its first sum.  Each node's sum runs in ascending
+// (element, local node) order: for every (z, y) candidate in ascending order,
+// element ex-1 before element ex (the order of the stored map's CSR sum, so
+// the lattice and map forms agree bitwise).
+//
+// The row and plane of a node come from divisions by the lattice extents,
+// fixed at launch (FastDiv: a multiply-high and a shift).  Along y (and z)
+// the candidates of lattice coordinate J are the element ey = min(J / p,
+// ny - 1) at local index ly = J - ey p and, when ly = 0 and ey > 0, also
+// element ey - 1 at local index p; their runs sit N^2 - p runs apart (N (ny N
+// - p) along z for the planes), so one base offset and two strides address
+// all four (y, z) runs.  The y/z branches are uniform over a wavefront except
+// where it crosses a row; the x-face word is loaded by every lane (the node's
+// own word when it is not on an x face) and selected.
+constexpr int kXRowsNodes = 2;
+
+struct XRowsGeom {
+  int nx, ny, nz;
+  int Lx, Ly, Lz;
+  FastDiv fLx, fLy;
+  int64_t n;
+};
+
+inline XRowsGeom xrows_geom(int nx, int ny, int nz, int p) {
+  XRowsGeom g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.Lx = nx * p + 1;
+  g.Ly = ny * p + 1;
+  g.Lz = nz * p + 1;
+  g.fLx = FastDiv(g.Lx);
+  g.fLy = FastDiv(g.Ly);
+  g.n = (int64_t)g.Lx * g.Ly * g.Lz;
+  return g;
+}
+
+// The loaded contributions of one node and what decides its sum.
+template <typename T>
+struct XRowsLoads {
+  T v[4], w[4];  // (z, y) candidates 0: (right, right) 1: (right, left) 2: (left, right) 3: (left, left)
+  bool hy, hz, xf, ess;
+};
+
+template <typename T, int P>
+__device__ __forceinline__ void xrows_load(const T* __restrict__ yX, const XRowsGeom& g, int i,
+                                           XRowsLoads<T>& L) {
+  constexpr int N = P + 1, W = xrows_width(N);
+  const int row = g.fLx.div(i), I = i - row * g.Lx;
+  const int K = g.fLy.div(row), J = row - K * g.Ly;
+  int ex = I / P, a = I - ex * P;
+  if (ex == g.nx) {  // the row's last node
+    ex = g.nx - 1;
+    a = P;
+  }
+  int ey = J / P, ez = K / P;
+  ey = ey < g.ny - 1 ? ey : g.ny - 1;
+  ez = ez < g.nz - 1 ? ez : g.nz - 1;
+  const int ly = J - ey * P, lz = K - ez * P;
+  L.hy = ly == 0 && ey > 0;
+  L.hz = lz == 0 && ez > 0;
+  L.xf = a == 0 && ex > 0;
+  L.ess = I == 0 || I == g.Lx - 1 || J == 0 || J == g.Ly - 1 || K == 0 || K == g.Lz - 1;
+  const int rowlen = g.nx * W;
+  const int o = (((ez * g.ny + ey) * N + lz) * N + ly) * rowlen + ex * W + a;
+  const int dy = (N * N - P) * rowlen, dz = N * (g.ny * N - P) * rowlen;
+  const int left = L.xf ? P - W : 0;
+  L.v[0] = yX[o];
+  L.w[0] = yX[o + left];
+  if (L.hy) {
+    L.v[1] = yX[o - dy];
+    L.w[1] = yX[o - dy + left];
+  }
+  if (L.hz) {
+    L.v[2] = yX[o - dz];
+    L.w[2] = yX[o - dz + left];
+    if (L.hy) {
+      L.v[3] = yX[o - dz - dy];
+      L.w[3] = yX[o - dz - dy + left];
+    }
+  }
+}
+
+// Sum of the loaded contributions in ascending (element, local node) order.
+template <typename T>
+__device__ __forceinline__ T xrows_sum(const XRowsLoads<T>& L) {
+  T acc = 0;
+  if (L.hz) {
+    if (L.hy) {
+      if (L.xf) acc += L.w[3];
+      acc += L.v[3];
+    }
+    if (L.xf) acc += L.w[2];
+    acc += L.v[2];
+  }
+  if (L.hy) {
+    if (L.xf) acc += L.w[1];
+    acc += L.v[1];
+  }
+  if (L.xf) acc += L.w[0];
+  acc += L.v[0];
+  return acc;
+}
+
+
 }  // namespace vec
 }  // namespace pafem

@@ -33,6 +33,11 @@ SOLVE_IR_FP32 = 1
 SOLVE_IR_BF16 = 2
 SOLVE_MIXED_FP32 = 3
 SOLVE_MIXED_BF16 = 4
+LAUNCH_KERNELS = 0
+ASSEMBLY_PARTIAL = 0
+ASSEMBLY_MATRIX_FREE = 1
+LAUNCH_GRAPH = 1
+LAUNCH_PERSISTENT = 2
 
 _ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "HIP", -4: "NOT_CONVERGED",
            -5: "UNSUPPORTED", -6: "NO_DEVICE"}
@@ -47,7 +52,8 @@ class PafemError(RuntimeError):
 
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("rtol", C.c_double), ("inner_rtol", C.c_double),
-                ("maxit", C.c_int), ("max_outer", C.c_int), ("check_every", C.c_int)]
+                ("maxit", C.c_int), ("max_outer", C.c_int), ("check_every", C.c_int),
+                ("launch", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -124,8 +130,10 @@ _SIGNATURES = {
     "pafem_op_set_coefficient_sinx": (_I, [_P, _D]),
     "pafem_op_assemble": (_I, [_P, _I, _P]),
     "pafem_op_qdata_bytes": (_I64, [_P, _I]),
+    "pafem_op_footprint_bytes": (_I64, [_P, _I]),
     "pafem_op_get_qdata": (_I, [_P, _I, _P, _P]),
     "pafem_op_set_scatter_mode": (_I, [_P, _I]),
+    "pafem_op_set_assembly_level": (_I, [_P, _I]),
     "pafem_op_set_restriction_mode": (_I, [_P, _I]),
     "pafem_op_apply": (_I, [_P, _I, _P, _P, _I, _P]),
     "pafem_op_apply_evector": (_I, [_P, _I, _P, _P, _I, _P]),
@@ -382,6 +390,9 @@ class Operator:
     def assemble(self, prec_mask: int = FP64, stream=None):
         _check(lib().pafem_op_assemble(self._h, prec_mask, _stream(stream)))
 
+    def footprint_bytes(self, prec_mask: int = FP64) -> int:
+        return lib().pafem_op_footprint_bytes(self._h, prec_mask)
+
     def qdata_bytes(self, prec_mask: int = FP64) -> int:
         return lib().pafem_op_qdata_bytes(self._h, prec_mask)
 
@@ -392,6 +403,9 @@ class Operator:
         out = torch.empty(self.space.nelems * self.ncomp * self.q ** 3, dtype=dt, device="cuda")
         _check(lib().pafem_op_get_qdata(self._h, prec, _dptr(out), _stream(stream)))
         return out.view(self.space.nelems, self.ncomp, self.q ** 3)
+
+    def set_assembly_level(self, level: int):
+        _check(lib().pafem_op_set_assembly_level(self._h, level))
 
     def set_scatter_mode(self, mode: int):
         _check(lib().pafem_op_set_scatter_mode(self._h, mode))
@@ -461,12 +475,13 @@ class Operator:
 
     def solve(self, b, x=None, mode: int = SOLVE_PLAIN_FP64, rtol: float = 1e-10,
               inner_rtol: float = 1e-4, maxit: int = 10000, max_outer: int = 50,
-              check_every: int = 1, stream=None, raise_on_nonconvergence: bool = True):
+              check_every: int = 1, stream=None, raise_on_nonconvergence: bool = True,
+              launch: int = LAUNCH_KERNELS):
         torch = self._torch()
         n = self.space.ndofs
         if x is None:
             x = torch.zeros(n, dtype=torch.float64, device="cuda")
-        o = SolveOpts(mode, rtol, inner_rtol, maxit, max_outer, check_every)
+        o = SolveOpts(mode, rtol, inner_rtol, maxit, max_outer, check_every, launch)
         st = SolveStats()
         rc = lib().pafem_solve_cg(self._h, _dptr(b, torch.float64, n, "b"),
                                   _dptr(x, torch.float64, n, "x"), C.byref(o), C.byref(st),

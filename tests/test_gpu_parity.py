@@ -287,7 +287,7 @@ def test_poisson_small_affine_plain_cg(pf, ctx):
     np.testing.assert_allclose(x, ref["x"], atol=1e-12 * np.abs(ref["x"]).max() * 100)
 
 
-@pytest.mark.parametrize("p", [3, 5])
+@pytest.mark.parametrize("p", [3, 5, 7])
 def test_poisson_perturbed_plain_and_mixed(pf, ctx, p):
     n = 4
     v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
@@ -297,12 +297,13 @@ def test_poisson_perturbed_plain_and_mixed(pf, ctx, p):
     mesh = pf.Mesh(ctx, n, n, n, v)
     op = pf.Operator(pf.Space(mesh, p), pf.DIFFUSION)
     op.set_coefficient_sinx(0.5)
-    op.assemble(pf.FP64 | pf.FP32)
+    op.assemble(pf.FP64 | pf.FP32 | pf.BF16)
     b = op.rhs()
     xr = ref["x"]
     its = {}
     for mode, inner in ((pf.SOLVE_PLAIN_FP64, 1e-3), (pf.SOLVE_IR_FP32, 1e-3),
-                        (pf.SOLVE_MIXED_FP32, 0.1)):
+                        (pf.SOLVE_MIXED_FP32, 0.1), (pf.SOLVE_MIXED_BF16, 0.1),
+                        (pf.SOLVE_IR_BF16, 1e-3)):
         x, st = op.solve(b, mode=mode, rtol=1e-10, inner_rtol=inner)
         assert st["true_rel_res"] <= 1e-10, (mode, st)
         err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
@@ -627,3 +628,28 @@ def test_fused_cg_full_size_solves_to_tolerance(pf, ctx):
         g = (ex * p) + L * (ey * p) + L * L * (ez * p) + loc
         ue = inputs.u_exact(Xn[:, 0], Xn[:, 1], Xn[:, 2])
         assert np.abs(xn[g] - ue).max() < 1e-6
+
+
+def test_footprint_counts_qdata_and_workspace(pf, ctx):
+    """The operator footprint is the quadrature data plus the E-vector, the
+    inverse diagonal, the CG vectors and the partials, and it covers what a
+    solve allocates."""
+    n, p = 6, 4
+    v = inputs.perturbed_vertices(n, n, n, seed=2)
+    op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, v), p), pf.DIFFUSION)
+    op.assemble(pf.FP64 | pf.FP32)
+    nd, ne = op.space.ndofs, op.space.nelems
+    q64 = ne * (p + 2) ** 3 * 6 * 8
+    assert op.qdata_bytes(pf.FP64) == q64
+    f64 = op.footprint_bytes(pf.FP64)
+    f32 = op.footprint_bytes(pf.FP64 | pf.FP32)
+    evec = ne * (p + 1) ** 3 * 8
+    assert f64 >= q64 + evec + nd * (8 + 4 * 8)
+    assert f32 - f64 == q64 // 2 + nd * 4 + nd * 16
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    b = op.rhs()
+    op.solve(b, mode=pf.SOLVE_MIXED_FP32, inner_rtol=0.1)
+    torch.cuda.synchronize()
+    grown = free0 - torch.cuda.mem_get_info()[0]
+    assert grown <= f32 - q64 - q64 // 2 + 8 * nd + (4 << 20)
