@@ -1,14 +1,17 @@
 // Serving engine: continuous batching of Poisson solves on one GPU.
 //
 // Host side: a request queue (thread-safe submit/poll), FIFO admission while a
-// slot is free and the request's device footprint fits the budget, and one
-// engine thread that owns all device work.  Device side: two batches (FP64
-// CG for plain requests; FP32-operator CG for the inner solves of refined
-// requests and for mixed requests, whose solution is kept in FP64 and whose
-// residual is replaced by the FP64 one between rounds);
-// every round replays one captured HIP graph per non-empty batch.  The graph's
-// kernels read the batch membership from a device table, so admission and
-// retirement only rewrite that table between replays.
+// slot is free and the request's device footprint fits the budget, an engine
+// thread that runs the rounds, and a setup thread that builds each admitted
+// request's operator, diagonal and right-hand side on its own stream while
+// the rounds of the others go on; a request joins its batch at the first
+// round boundary after its setup has completed.  Device side: two batches
+// (FP64 CG for plain requests; FP32-operator CG for the inner solves of
+// refined requests and for mixed requests, whose solution is kept in FP64 and
+// whose residual is replaced by the FP64 one between rounds), each replaying
+// one captured HIP graph per round on its own stream.  The graph's kernels
+// read the batch membership from a device table, so admission and retirement
+// only rewrite that table between replays.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,9 +108,20 @@ struct Server {
   int startup_error = 0;
   std::string startup_message;
 
-  // engine thread
+  // engine thread; the FP64 batch and the per-request work between rounds run
+  // on `stream`, the FP32 batch on `stream32`
   std::thread th;
   hipStream_t stream = nullptr;
+  hipStream_t stream32 = nullptr;
+  hipEvent_t main_done = nullptr;  // orders the FP32 batch after the work between rounds
+  // setup worker: admitted requests build their operator, diagonal and
+  // right-hand side on `setup_stream` while the rounds of the others go on
+  std::thread setup_th;
+  hipStream_t setup_stream = nullptr;
+  std::deque<Req*> to_setup;                 // guarded by mu
+  std::vector<std::pair<Req*, int>> ready;   // set up (or failed), guarded by mu
+  int setting_up = 0;                        // admitted, not yet in a batch (engine only)
+  std::condition_variable cv_setup;
   DevBuf d_states;                 // CgState[max_slots]
   CgState* h_states = nullptr;     // pinned mirror
   std::vector<int> free_slots;
@@ -258,7 +272,13 @@ BatchEntry<T> as_offsets(const void* base, BatchEntry<T> e) {
 // order's element pass is its own launch over its range of work items), in
 // admission order within an order.
 template <typename T>
+hipStream_t batch_stream(const Server& S) {
+  return std::is_same<T, float>::value ? S.stream32 : S.stream;
+}
+
+template <typename T>
 int batch_upload(Server& S, Batch<T>& b) {
+  const hipStream_t bs = batch_stream<T>(S);
   int64_t w = 0, c = 0;
   size_t i = 0;
   for (int p = 1; p <= kMaxP; ++p) {
@@ -279,63 +299,76 @@ int batch_upload(Server& S, Batch<T>& b) {
   if (!b.members.empty())
     PAFEM_TRY_HIP(hipMemcpyAsync(b.d_entries.ptr, b.h_entries,
                                  sizeof(BatchEntry<T>) * b.members.size(),
-                                 hipMemcpyHostToDevice, S.stream));
+                                 hipMemcpyHostToDevice, bs));
   PAFEM_TRY_HIP(hipMemcpyAsync(b.d_hdr.ptr, b.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice,
-                               S.stream));
+                               bs));
   // the pinned staging is reused next round: wait for the copies to leave it
-  PAFEM_TRY_HIP(hipStreamSynchronize(S.stream));
+  PAFEM_TRY_HIP(hipStreamSynchronize(bs));
   b.dirty = false;
+  return PAFEM_OK;
+}
+
+// The K iterations of a batch as one graph.  Its launch shapes do not depend
+// on the members (the kernels read the table), so it is captured once, when
+// the server is created and before its threads start: no capture is ever in
+// progress while the setup thread makes synchronous calls.
+template <typename T>
+int batch_capture(Server& S, Batch<T>& b) {
+  const hipStream_t bs = batch_stream<T>(S);
+  PAFEM_TRY_HIP(hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+  hipError_t le = launch_batch_iterations<T>(b.d_entries.template as<BatchEntry<T>>(),
+                                             b.d_hdr.template as<BatchHeader>(), S.max_slots,
+                                             S.iters, bs);
+  hipError_t ce = hipStreamEndCapture(bs, &b.graph);
+  PAFEM_TRY_HIP(le);
+  PAFEM_TRY_HIP(ce);
+  PAFEM_TRY_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
   return PAFEM_OK;
 }
 
 template <typename T>
 int batch_round(Server& S, Batch<T>& b) {
   if (b.members.empty()) return PAFEM_OK;
+  const hipStream_t bs = batch_stream<T>(S);
   if (b.dirty) PAFEM_TRY(batch_upload(S, b));
-  if (!b.exec) {
-    PAFEM_TRY_HIP(hipStreamBeginCapture(S.stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_batch_iterations<T>(b.d_entries.template as<BatchEntry<T>>(),
-                                               b.d_hdr.template as<BatchHeader>(), S.max_slots,
-                                               S.iters, S.stream);
-    hipError_t ce = hipStreamEndCapture(S.stream, &b.graph);
-    PAFEM_TRY_HIP(le);
-    PAFEM_TRY_HIP(ce);
-    PAFEM_TRY_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-  }
-  PAFEM_TRY_HIP(hipGraphLaunch(b.exec, S.stream));
+  PAFEM_TRY_HIP(hipGraphLaunch(b.exec, bs));
   return PAFEM_OK;
 }
 
 // CG start on the request's slot: r holds the right-hand side of this solve,
 // x its zero initial guess; bb scales the stopping test.
 template <typename T>
-int cg_start(Server& S, Req* r, T* rr, T* dir, const T* dinv, double bb, double rtol) {
+int cg_start(Server& S, Req* r, T* rr, T* dir, const T* dinv, double bb, double rtol,
+             hipStream_t s) {
   const int nb = reduce_blocks(r->ndofs);
-  PAFEM_TRY_HIP(launch_cg_init<T>(rr, dinv, dir, r->ndofs, r->partials(), nb, S.stream));
+  PAFEM_TRY_HIP(launch_cg_init<T>(rr, dinv, dir, r->ndofs, r->partials(), nb, s));
   PAFEM_TRY_HIP(launch_cg_init_final(r->partials(), nb, bb, rtol, r->spec.maxit,
-                                     S.d_states.as<CgState>() + r->slot, S.stream));
+                                     S.d_states.as<CgState>() + r->slot, s));
   return PAFEM_OK;
 }
 
-int dot_to_host(Server& S, Req* r, const double* a, const double* b, double* dev, double& out) {
+int dot_to_host(Req* r, const double* a, const double* b, double* dev, double& out,
+                hipStream_t s) {
   const int nb = reduce_blocks(r->ndofs);
-  PAFEM_TRY_HIP(launch_dot_partial<double>(a, b, r->ndofs, r->partials(), nb, nullptr, S.stream));
-  PAFEM_TRY_HIP(launch_sum_final(r->partials(), nb, 1, dev, S.stream));
-  PAFEM_TRY_HIP(hipMemcpyAsync(&out, dev, sizeof(double), hipMemcpyDeviceToHost, S.stream));
-  PAFEM_TRY_HIP(hipStreamSynchronize(S.stream));
+  PAFEM_TRY_HIP(launch_dot_partial<double>(a, b, r->ndofs, r->partials(), nb, nullptr, s));
+  PAFEM_TRY_HIP(launch_sum_final(r->partials(), nb, 1, dev, s));
+  PAFEM_TRY_HIP(hipMemcpyAsync(&out, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  PAFEM_TRY_HIP(hipStreamSynchronize(s));
   return PAFEM_OK;
 }
 
 // Inner FP32 solve of A d = r / ||r|| with d = 0 to start.
-int start_inner(Server& S, Req* r) {
+int start_inner(Server& S, Req* r, hipStream_t s) {
   const int64_t n = r->ndofs;
-  PAFEM_TRY_HIP(launch_scale_to_f32(r->r(), r->rr_dev(), r->r32(), n, S.stream));
-  PAFEM_TRY_HIP(launch_fill<float>(r->d32(), n, 0.0f, nullptr, S.stream));
+  PAFEM_TRY_HIP(launch_scale_to_f32(r->r(), r->rr_dev(), r->r32(), n, s));
+  PAFEM_TRY_HIP(launch_fill<float>(r->d32(), n, 0.0f, nullptr, s));
   return cg_start<float>(S, r, r->r32(), r->dir32(), r->op->d_dinv32.as<float>(), 1.0,
-                         r->spec.inner_rtol);
+                         r->spec.inner_rtol, s);
 }
 
-int setup(Server& S, Req* r) {
+// Build a request's operator, diagonal, right-hand side and CG start on
+// stream s (synchronous on s only).
+int setup(Server& S, Req* r, hipStream_t s) {
   const pafem_request& q = r->spec;
   PAFEM_TRY(pafem_mesh_create_structured(S.ctx, q.nx, q.ny, q.nz, r->verts.data(), &r->mesh));
   PAFEM_TRY(pafem_space_create(r->mesh, q.p, &r->space));
@@ -345,33 +378,33 @@ int setup(Server& S, Req* r) {
   else
     PAFEM_TRY(pafem_op_set_coefficient_const(r->op, q.coef_value));
   const bool f32 = r->ir || r->mixed;
-  PAFEM_TRY(pafem_op_assemble(r->op, PAFEM_FP64 | (f32 ? PAFEM_FP32 : 0), S.stream));
+  PAFEM_TRY(pafem_op_assemble(r->op, PAFEM_FP64 | (f32 ? PAFEM_FP32 : 0), s));
   const int64_t n = r->ndofs;
   PAFEM_TRY(r->v64.ensure(5 * n * sizeof(double)));
   if (f32) PAFEM_TRY(r->v32.ensure(4 * n * sizeof(float)));
   PAFEM_TRY(r->part.ensure((r->nparts() + 8) * sizeof(double)));
-  PAFEM_TRY(pafem_rhs_assemble(r->op, nullptr, r->b(), S.stream));
-  PAFEM_TRY(ensure_dinv(r->op, S.stream, f32));
-  PAFEM_TRY_HIP(launch_fill<double>(r->x(), n, 0.0, nullptr, S.stream));
+  PAFEM_TRY(pafem_rhs_assemble(r->op, nullptr, r->b(), s));
+  PAFEM_TRY(ensure_dinv(r->op, s, f32));
+  PAFEM_TRY_HIP(launch_fill<double>(r->x(), n, 0.0, nullptr, s));
   PAFEM_TRY_HIP(hipMemcpyAsync(r->r(), r->b(), n * sizeof(double), hipMemcpyDeviceToDevice,
-                               S.stream));
-  PAFEM_TRY(dot_to_host(S, r, r->b(), r->b(), r->rr_dev(), r->bb));
+                               s));
+  PAFEM_TRY(dot_to_host(r, r->b(), r->b(), r->rr_dev(), r->bb, s));
   if (r->mixed) {
     // x = 0: the FP64 residual is b; rs = (float) b, dir = dinv .* rs
     const int nb = reduce_blocks(n);
     CgState* st = S.d_states.as<CgState>() + r->slot;
     const float* dinv32 = r->op->d_dinv32.as<float>();
     PAFEM_TRY_HIP(launch_replace_residual(r->r(), dinv32, r->r32(), n, r->partials(), nb, nullptr,
-                                          S.stream));
-    PAFEM_TRY_HIP(launch_cg_init_final(r->partials(), nb, r->bb, q.rtol, q.maxit, st, S.stream,
+                                          s));
+    PAFEM_TRY_HIP(launch_cg_init_final(r->partials(), nb, r->bb, q.rtol, q.maxit, st, s,
                                        q.inner_rtol * q.inner_rtol));
-    PAFEM_TRY_HIP(launch_fill<float>(r->dir32(), n, 0.0f, nullptr, S.stream));
-    PAFEM_TRY_HIP(launch_cg_pupdate<float>(r->dir32(), r->r32(), dinv32, n, st, S.stream));
+    PAFEM_TRY_HIP(launch_fill<float>(r->dir32(), n, 0.0f, nullptr, s));
+    PAFEM_TRY_HIP(launch_cg_pupdate<float>(r->dir32(), r->r32(), dinv32, n, st, s));
     return PAFEM_OK;
   }
-  if (r->ir) return start_inner(S, r);  // rr_dev holds ||r||^2 = ||b||^2
+  if (r->ir) return start_inner(S, r, s);  // rr_dev holds ||r||^2 = ||b||^2
   return cg_start<double>(S, r, r->r(), r->dir(), r->op->d_dinv64.as<double>(), r->bb,
-                          q.rtol);
+                          q.rtol, s);
 }
 
 void release_device(Server& S, Req* r) {
@@ -439,7 +472,7 @@ int true_residual(Server& S, Req* r, double& rel) {
                                S.stream));
   PAFEM_TRY_HIP(launch_residual(r->b(), r->Ad(), r->r(), r->ndofs, S.stream));
   double rr = 0.0;
-  PAFEM_TRY(dot_to_host(S, r, r->r(), r->r(), r->rr_dev(), rr));
+  PAFEM_TRY(dot_to_host(r, r->r(), r->r(), r->rr_dev(), rr, S.stream));
   rel = r->bb > 0.0 ? std::sqrt(rr / r->bb) : std::sqrt(rr);
   return PAFEM_OK;
 }
@@ -522,8 +555,32 @@ void on_cg_done(Server& S, Req* r, const CgState& st) {
   }
   if (rel <= r->spec.rtol) return finish(S, r, PAFEM_OK, true);
   if (r->outer >= r->spec.max_outer) return finish(S, r, PAFEM_ERR_NOT_CONVERGED, true);
-  rc = start_inner(S, r);
+  rc = start_inner(S, r, S.stream);
   if (rc != PAFEM_OK) finish(S, r, rc, false);
+}
+
+// Setup worker: admitted requests are set up here, one at a time, while the
+// engine keeps replaying rounds for the others.
+void setup_worker(Server& S) {
+  (void)hipSetDevice(S.device);
+  for (;;) {
+    Req* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S.mu);
+      S.cv_setup.wait(lk, [&] { return S.stopping || !S.to_setup.empty(); });
+      if (S.to_setup.empty()) return;  // stopping and nothing left
+      r = S.to_setup.front();
+      S.to_setup.pop_front();
+    }
+    int rc = setup(S, r, S.setup_stream);
+    // the batches run on other streams: the setup must be complete first
+    if (hipStreamSynchronize(S.setup_stream) != hipSuccess && rc == PAFEM_OK) rc = PAFEM_ERR_HIP;
+    {
+      std::lock_guard<std::mutex> g(S.mu);
+      S.ready.emplace_back(r, rc);
+    }
+    S.cv_work.notify_all();
+  }
 }
 
 void engine(Server& S) {
@@ -532,6 +589,7 @@ void engine(Server& S) {
     // ---- admission (FIFO while a slot is free and the footprint fits) ----
     std::vector<Req*> admit;
     std::vector<Req*> reject;
+    std::vector<std::pair<Req*, int>> ready;
     {
       std::unique_lock<std::mutex> lk(S.mu);
       while (!S.queue.empty()) {
@@ -541,7 +599,7 @@ void engine(Server& S) {
           reject.push_back(r);
           continue;
         }
-        if ((int)(S.active.size() + admit.size()) >= S.max_slots) break;
+        if ((int)(S.active.size() + S.setting_up + admit.size()) >= S.max_slots) break;
         if (S.used + r->footprint > S.budget) break;
         S.queue.pop_front();
         S.used += r->footprint;
@@ -550,8 +608,17 @@ void engine(Server& S) {
         r->t_admit = S.now();
         admit.push_back(r);
       }
-      if (S.active.empty() && admit.empty() && reject.empty()) {
-        if (S.stopping) break;
+      // the slot is reserved before the setup thread can see the request: the
+      // setup writes that slot's CG state
+      for (Req* r : admit) {
+        r->slot = S.free_slots.back();
+        S.free_slots.pop_back();
+        ++S.setting_up;
+        S.to_setup.push_back(r);
+      }
+      ready.swap(S.ready);
+      if (S.active.empty() && admit.empty() && reject.empty() && ready.empty()) {
+        if (S.stopping && S.setting_up == 0) break;
         S.cv_work.wait_for(lk, std::chrono::milliseconds(20));
         continue;
       }
@@ -560,13 +627,13 @@ void engine(Server& S) {
       r->footprint = 0;  // nothing was reserved
       finish(S, r, PAFEM_ERR_OUT_OF_MEMORY, false);
     }
-    for (Req* r : admit) {
-      r->slot = S.free_slots.back();
-      S.free_slots.pop_back();
+    if (!admit.empty()) S.cv_setup.notify_all();
+    for (auto& rr : ready) {
+      Req* r = rr.first;
+      --S.setting_up;
       S.active.push_back(r);
-      int rc = setup(S, r);
-      if (rc != PAFEM_OK) {
-        finish(S, r, rc, false);
+      if (rr.second != PAFEM_OK) {
+        finish(S, r, rr.second, false);
         continue;
       }
       if (r->ir || r->mixed) {
@@ -582,9 +649,15 @@ void engine(Server& S) {
       S.max_active = std::max(S.max_active, (int)S.active.size());
     }
     if (S.active.empty()) continue;
-    // ---- one round: K CG iterations for every batch member ----
+    // ---- one round: K CG iterations for every batch member, the FP64 and
+    // the FP32 batch on their own streams ----
     int rc = batch_round(S, S.b64);
+    // the FP32 batch follows the work enqueued on the main stream between rounds
+    if (rc == PAFEM_OK && (hipEventRecord(S.main_done, S.stream) != hipSuccess ||
+                           hipStreamWaitEvent(S.stream32, S.main_done, 0) != hipSuccess))
+      rc = PAFEM_ERR_HIP;
     if (rc == PAFEM_OK) rc = batch_round(S, S.b32);
+    if (rc == PAFEM_OK && hipStreamSynchronize(S.stream32) != hipSuccess) rc = PAFEM_ERR_HIP;
     if (rc == PAFEM_OK &&
         (hipMemcpyAsync(S.h_states, S.d_states.ptr, sizeof(CgState) * S.max_slots,
                         hipMemcpyDeviceToHost, S.stream) != hipSuccess ||
@@ -651,24 +724,36 @@ int pafem_server_create(pafem_ctx* ctx, int64_t budget, int max_slots, int iters
   S->iters = iters;
   S->t0 = Clock::now();
   int rc = PAFEM_OK;
-  if (hipStreamCreate(&S->stream) != hipSuccess) rc = PAFEM_ERR_HIP;
+  // non-blocking streams: a synchronous copy of the setup thread on the null
+  // stream neither waits for the rounds nor joins them
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->stream32, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->setup_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&S->main_done, hipEventDisableTiming) != hipSuccess)
+    rc = PAFEM_ERR_HIP;
   if (rc == PAFEM_OK) rc = S->d_states.ensure(sizeof(CgState) * max_slots);
   if (rc == PAFEM_OK &&
       hipHostMalloc((void**)&S->h_states, sizeof(CgState) * max_slots) != hipSuccess)
     rc = PAFEM_ERR_HIP;
   if (rc == PAFEM_OK) rc = batch_init(S->b64, max_slots);
   if (rc == PAFEM_OK) rc = batch_init(S->b32, max_slots);
+  if (rc == PAFEM_OK) rc = batch_capture(*S, S->b64);
+  if (rc == PAFEM_OK) rc = batch_capture(*S, S->b32);
   if (rc != PAFEM_OK) {
     batch_free(S->b64);
     batch_free(S->b32);
     if (S->h_states) (void)hipHostFree(S->h_states);
     if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->stream32) (void)hipStreamDestroy(S->stream32);
+    if (S->setup_stream) (void)hipStreamDestroy(S->setup_stream);
+    if (S->main_done) (void)hipEventDestroy(S->main_done);
     delete S;
     if (rc == PAFEM_ERR_HIP) set_error("HIP error creating the server");
     return rc;
   }
   for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
   ++ctx->refs;
+  S->setup_th = std::thread([S] { setup_worker(*S); });
   S->th = std::thread([S] { engine(*S); });
   *out = S;
   return PAFEM_OK;
@@ -798,12 +883,17 @@ int pafem_server_destroy(pafem_server* S) {
     S->stopping = true;
   }
   S->cv_work.notify_all();
+  S->cv_setup.notify_all();
   if (S->th.joinable()) S->th.join();
+  if (S->setup_th.joinable()) S->setup_th.join();
   (void)hipSetDevice(S->device);
   batch_free(S->b64);
   batch_free(S->b32);
   if (S->h_states) (void)hipHostFree(S->h_states);
   if (S->stream) (void)hipStreamDestroy(S->stream);
+  if (S->stream32) (void)hipStreamDestroy(S->stream32);
+  if (S->setup_stream) (void)hipStreamDestroy(S->setup_stream);
+  if (S->main_done) (void)hipEventDestroy(S->main_done);
   pafem_ctx* ctx = S->ctx;
   delete S;
   pafem_ctx_destroy(ctx);  // drops the server's reference
