@@ -22,9 +22,20 @@ The same JSON line also reports
     of a small Poisson solve (4^3 affine mesh, p = 2);
   * sweep: FP64 diffusion/mass and FP32 diffusion apply GDOF/s for p = 1..8 at
     about 8M dofs;
-  * serving: a seeded Poisson-arrival stream of Poisson solves (N in 8..20,
-    p in 2..8) submitted in real time to the continuous-batching server, with
-    p50/p99 latency and aggregate GDOF/s per arrival rate.
+  * sweep: the same at about 1M and 64M dofs (FP64 diffusion and mass,
+    whole-apply GDOF/s and fraction of the HBM roofline);
+  * mixed_30M: plain FP64 CG against the mixed-precision forms at p = 3, 5, 7
+    on ~30M-dof meshes, constant and variable coefficient;
+  * pmg: the p-multigrid preconditioned (flexible) CG to 1e-10 against
+    Jacobi-PCG on the headline problem and on the p=7 64^3 problem;
+  * cg_launch_forms: GDOF/s per CG iteration against problem size for the
+    separate-kernel, graph-replayed and persistent forms;
+  * serving: a seeded Poisson-arrival stream of Poisson solves (N in 8..64,
+    p in 2..8) submitted in real time to the continuous-batching server at
+    rates set from its measured capacity, with p50/p99 latency and aggregate
+    GDOF/s per rate;
+  * config0_oracle: CPU seconds of the oracle's 4^3, p=2 Poisson solve, and
+    an all-cores CSR SpMV figure beside the one-core oracle baseline.
 """
 from __future__ import annotations
 
@@ -149,6 +160,51 @@ def cpu_oracle_baseline(p, N, seconds_target=12.0):
                        f"not included")}
 
 
+def cpu_all_cores_spmv(p, N, seconds_target=5.0):
+    """All-cores CSR SpMV (oracle/csr_spmv.c, OpenMP) on the oracle's matrix."""
+    import ctypes as C
+    from oracle import build_csr, fem
+    from paper_2402_15940_amd import inputs
+    lib_path = build_csr.LIB if os.path.exists(build_csr.LIB) else build_csr.build()
+    lib = C.CDLL(lib_path)
+    v = inputs.perturbed_vertices(N, N, N, seed=inputs.mesh_seed(p, N))
+    A = fem.assemble("diffusion", v, N, N, N, p)
+    x = inputs.random_vector(A.shape[0], inputs.vector_seed(p, N))
+    y = np.empty_like(x)
+    rp = A.indptr.astype(np.int64)
+    ci = A.indices.astype(np.int32)
+    args = (C.c_int64(A.shape[0]), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+            A.data.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p),
+            y.ctypes.data_as(C.c_void_p))
+    lib.csr_spmv(*args)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        lib.csr_spmv(*args)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or reps >= 5000:
+            break
+    return {"value": A.shape[0] / (el / reps) / 1e9, "unit": "GDOF/s", "cores": lib.csr_threads(),
+            "host_cpu_count": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "sample": f"OpenMP CSR SpMV of the same {A.shape[0]}-dof p={p} matrix, {reps} applies"}
+
+
+def config0_oracle_seconds():
+    """CPU seconds of the oracle's Poisson solve on the 4^3 affine mesh, p = 2 (assembly,
+    right-hand side and Jacobi-PCG to 1e-10), median of 5."""
+    from oracle import fem
+    from paper_2402_15940_amd import inputs
+    v = inputs.perturbed_vertices(4, 4, 4, seed=None)
+    ts, res = [], None
+    for _ in range(5):
+        t0 = time.perf_counter()
+        res = fem.solve_poisson(v, 4, 4, 4, 2, f=inputs.f_manufactured, rtol=1e-10)
+        ts.append(time.perf_counter() - t0)
+    return {"problem": "4^3 affine mesh, p=2, q=4, 729 dofs, Jacobi-PCG to 1e-10",
+            "cpu_seconds_median": round(float(np.median(ts)), 5), "cores": 1,
+            "iterations": res["iterations"], "true_rel_res": float(f"{res['true_rel_res']:.4g}")}
+
+
 def serve_benchmark(pf, ctx, rate, n_req, n_range, p_range, budget, max_slots, iters):
     """Submit a seeded Poisson-arrival stream of Poisson solves in real time; report
     p50/p99 latency (arrival to done, server clock) and aggregate GDOF/s."""
@@ -185,6 +241,207 @@ def serve_benchmark(pf, ctx, rate, n_req, n_range, p_range, budget, max_slots, i
             "mean_ndofs": int(np.mean([r["ndofs"] for r in res]))}
 
 
+def whole_apply_frac(ne, n, q, ncomp, ndofs, ms):
+    return apply_bytes(ne, n, q, ncomp, ndofs, 8) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+
+def sweep_applies(torch, pf, ctx, target, mode, steps):
+    """FP64 diffusion and mass apply over p = 1..8 at about `target` dofs (one
+    operator resident at a time)."""
+    rows = []
+    for pp in range(1, 9):
+        NN = inputs_mod().mesh_n_for_dofs(pp, target)
+        v = inputs_mod().perturbed_vertices(NN, NN, NN, seed=inputs_mod().mesh_seed(pp, NN))
+        spp = pf.Space(pf.Mesh(ctx, NN, NN, NN, v), pp)
+        nd, nee = spp.ndofs, spp.nelems
+        xx = torch.from_numpy(inputs_mod().random_vector(nd, inputs_mod().vector_seed(pp, NN))).cuda()
+        yy = torch.empty_like(xx)
+        row = {"p": pp, "N": NN, "ndofs": nd}
+        for kind in ("diffusion", "mass"):
+            op = pf.Operator(spp, pf.DIFFUSION if kind == "diffusion" else pf.MASS)
+            op.assemble(pf.FP64)
+            op.set_scatter_mode(mode)
+            _, msw = time_applies(torch, op, xx, yy, steps, 2)
+            row[f"{kind}_fp64_gdofs"] = round(nd / (msw * 1e-3) / 1e9, 3)
+            row[f"{kind}_fp64_apply_hbm_frac"] = round(
+                whole_apply_frac(nee, pp + 1, pp + 2, 6 if kind == "diffusion" else 1, nd, msw), 4)
+            del op
+            torch.cuda.synchronize()
+        rows.append(row)
+        log(f"sweep {target:.0e}: {row}")
+        del spp, xx, yy
+        torch.cuda.synchronize()
+    return rows
+
+
+def inputs_mod():
+    from paper_2402_15940_amd import inputs
+    return inputs
+
+
+def launch_form_curve(torch, pf, ctx):
+    """GDOF/s per FP64 Jacobi-PCG iteration (p = 6 diffusion, perturbed meshes)
+    against ndofs for the three launch forms, from the difference of two run
+    lengths (50 and 250 iterations, 50 per host check)."""
+    inputs = inputs_mod()
+    p = 6
+    forms = (("kernels", pf.LAUNCH_KERNELS), ("graph", pf.LAUNCH_GRAPH),
+             ("persistent", pf.LAUNCH_PERSISTENT))
+    rows = []
+    for N in (3, 4, 6, 9, 14, 21, 33):
+        v = inputs.perturbed_vertices(N, N, N, seed=inputs.mesh_seed(p, N))
+        op = pf.Operator(pf.Space(pf.Mesh(ctx, N, N, N, v), p), pf.DIFFUSION)
+        op.assemble(pf.FP64)
+        nd = op.space.ndofs
+        b = op.rhs()
+        row = {"N": N, "ndofs": nd}
+        for name, form in forms:
+            def run(k):
+                x = torch.zeros_like(b)
+                _, st = op.solve(b, x, rtol=1e-30, maxit=k, check_every=50, launch=form,
+                                 raise_on_nonconvergence=False)
+                return st
+            run(50)
+            s1, s2 = run(50), run(250)
+            t_it = (s2["seconds"] - s1["seconds"]) / (s2["iterations"] - s1["iterations"])
+            row[f"{name}_us_per_iter"] = round(t_it * 1e6, 2)
+            row[f"{name}_gdofs"] = round(nd / t_it / 1e9, 4)
+        rows.append(row)
+        log(f"launch forms {row}")
+        del op, b
+        torch.cuda.synchronize()
+    marks = {}
+    for name, _ in forms:
+        top = rows[-1][f"{name}_gdofs"]
+        first = next((r["ndofs"] for r in rows if r[f"{name}_gdofs"] >= 0.8 * top), None)
+        marks[name] = {"large_size_gdofs": top, "ndofs_at_80pct": first}
+    return {"operator": "FP64 diffusion, p=6, perturbed meshes N^3, N in 3..33",
+            "rows": rows, "reaches_80pct_of_large_size_rate": marks}
+
+
+def mixed_precision_configs(torch, pf, ctx, mode):
+    """Plain FP64 CG vs the mixed-precision forms to 1e-10 at p = 3, 5, 7 on
+    about 30M dofs, constant and variable coefficient."""
+    inputs = inputs_mod()
+    out = []
+    for pp, NN in ((3, 103), (5, 62), (7, 44)):
+        v = inputs.perturbed_vertices(NN, NN, NN, seed=inputs.mesh_seed(pp, NN))
+        spp = pf.Space(pf.Mesh(ctx, NN, NN, NN, v), pp)
+        for coef in ("const", "sinx"):
+            op = pf.Operator(spp, pf.DIFFUSION)
+            if coef == "sinx":
+                op.set_coefficient_sinx(0.5)
+            op.assemble(pf.FP64 | pf.FP32 | pf.BF16)
+            op.set_scatter_mode(mode)
+            b = op.rhs()
+            res, x64 = {}, None
+            for name, md, inner in (("plain_fp64", pf.SOLVE_PLAIN_FP64, 1e-4),
+                                    ("ir_fp32", pf.SOLVE_IR_FP32, 1e-4),
+                                    ("mixed_fp32", pf.SOLVE_MIXED_FP32, 0.1),
+                                    ("mixed_bf16", pf.SOLVE_MIXED_BF16, 0.1)):
+                x = torch.zeros_like(b)
+                _, st = op.solve(b, x, mode=md, rtol=1e-10, inner_rtol=inner, maxit=100000,
+                                 max_outer=200, check_every=50)
+                r = {k: (float(f"{v_:.4g}") if isinstance(v_, float) else v_) for k, v_ in st.items()}
+                if x64 is None:
+                    x64 = x
+                else:
+                    r["rel_diff_vs_plain"] = float((x - x64).norm() / x64.norm())
+                    r["speedup_vs_plain"] = round(res["plain_fp64"]["seconds"] / st["seconds"], 3)
+                res[name] = r
+            row = {"p": pp, "N": NN, "ndofs": spp.ndofs, "coefficient": coef, "solves": res}
+            out.append(row)
+            log(f"mixed 30M {row}")
+            del op, b, x, x64
+            torch.cuda.synchronize()
+        del spp
+    return out
+
+
+def pmg_solve(torch, pf, op, b, jacobi=None):
+    """p-multigrid flexible CG to 1e-10 (hierarchy built and timed here)."""
+    t0 = time.perf_counter()
+    mg = pf.Multigrid(op)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    x = torch.zeros_like(b)
+    _, st = mg.solve(b, x, rtol=1e-10, maxit=2000)
+    out = {"levels": [mg.level_info(k) for k in range(mg.num_levels)],
+           "setup_seconds": round(setup, 4),
+           "iterations": st["iterations"], "seconds": round(st["seconds"], 4),
+           "true_rel_res": float(f"{st['true_rel_res']:.4g}"),
+           "options": {"cheb_degree": mg.opts.cheb_degree, "cheb_lower": mg.opts.cheb_lower,
+                       "lmax_safety": mg.opts.lmax_safety, "power_iters": mg.opts.power_iters,
+                       "coarse_iters": mg.opts.coarse_iters}}
+    if jacobi is not None:
+        xj, sj = jacobi
+        out["jacobi_pcg"] = {"iterations": sj["iterations"], "seconds": round(sj["seconds"], 4)}
+        out["speedup_vs_jacobi"] = round(sj["seconds"] / st["seconds"], 3)
+        out["speedup_vs_jacobi_with_setup"] = round(sj["seconds"] / (st["seconds"] + setup), 3)
+        out["rel_diff_vs_jacobi"] = float((x - xj).norm() / xj.norm())
+    mg.close()
+    return out
+
+
+def serving_configs(pf, ctx, n_req, fracs, budget, slots, iters):
+    """Capacity from a burst of the stream, then the stream at rates set from it."""
+    burst = serve_benchmark(pf, ctx, 1e6, n_req, (8, 64), (2, 8), budget, slots, iters)
+    cap = burst["solves_per_s"]
+    log(f"serving burst (capacity) {burst}")
+    runs = []
+    for f in fracs:
+        r = serve_benchmark(pf, ctx, f * cap, n_req, (8, 64), (2, 8), budget, slots, iters)
+        r["rate_fraction_of_capacity"] = f
+        runs.append(r)
+        log(f"serving {r}")
+    return {"capacity_burst": burst, "runs": runs}
+
+
+def profile_run(torch, pf, ctx, p, steps):
+    """The kernels the counter summaries under profiles/ cover, each launched
+    `steps` times (after one warm-up) on a ~8M-dof mesh of order p."""
+    from paper_2402_15940_amd import inputs
+    N = inputs.mesh_n_for_dofs(p, 8e6)
+    v = inputs.perturbed_vertices(N, N, N, seed=inputs.mesh_seed(p, N))
+    sp = pf.Space(pf.Mesh(ctx, N, N, N, v), p)
+    K = pf.Operator(sp, pf.DIFFUSION)
+    K.assemble(pf.FP64)
+    M = pf.Operator(sp, pf.MASS)
+    M.assemble(pf.FP64)
+    Kmf = pf.Operator(sp, pf.DIFFUSION)
+    Kmf.set_assembly_level(pf.ASSEMBLY_MATRIX_FREE)
+    Kmf.assemble(pf.FP64)
+    x = torch.from_numpy(inputs.random_vector(sp.ndofs, inputs.vector_seed(p, N))).cuda()
+    y = torch.empty_like(x)
+    out = {"p": p, "N": N, "ndofs": sp.ndofs, "elements": sp.nelems}
+    ms, _ = time_applies(torch, K, x, y, steps, 1)
+    out["diffusion_apply_ms"] = round(ms, 5)
+    ms, _ = time_applies(torch, M, x, y, steps, 1)
+    out["mass_apply_ms"] = round(ms, 5)
+    ms, _ = time_applies(torch, Kmf, x, y, steps, 1)
+    out["diffusion_matrix_free_apply_ms"] = round(ms, 5)
+    K.set_scatter_mode(pf.SCATTER_ATOMIC)
+    ms, _ = time_applies(torch, K, x, y, steps, 1)
+    out["diffusion_atomic_apply_ms"] = round(ms, 5)
+    nbytes = 1 << 30
+    ca = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    acc = torch.zeros((), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        acc += ca.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        acc += ca.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    out["stream_read_gbs"] = round(nbytes / (e0.elapsed_time(e1) / 3 * 1e-3) / 1e9, 1)
+    print(json.dumps({"profile_run": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,12 +455,23 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the p=7 64^3 (90M dofs) single solve")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", type=str, default="20,80,320",
-                    help="arrival rates (requests/s) of the serving stream")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-fracs", type=str, default="0.5,1.1",
+                    help="arrival rates of the serving stream as fractions of its measured capacity "
+                         "(the full sweep is 0.25,0.5,0.75,0.9,1.1)")
+    ap.add_argument("--serve-requests", type=int, default=8,
+                    help="requests per rate (cut from the 2,000 of the full stream to keep the run "
+                         "within minutes: the mean request has about 25M dofs)")
+    ap.add_argument("--no-64m", action="store_true", help="skip the 64M-dof apply sweep")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the ~30M-dof mixed-precision solves")
+    ap.add_argument("--no-curve", action="store_true", help="skip the CG launch-form size curve")
     ap.add_argument("--scatter", choices=["atomic", "deterministic"], default="deterministic")
     ap.add_argument("--copy-only", action="store_true",
                     help="stop after the headline applies and the copy reference (profiling runs)")
+    ap.add_argument("--profile", type=int, default=0, metavar="P",
+                    help="profiling run at order P (~8M dofs): FP64 diffusion apply, its element "
+                         "pass with atomic E^T, FP64 mass apply, matrix-free diffusion apply, a "
+                         "1 GiB copy and a 1 GiB streaming read, --steps times each; prints a "
+                         "short summary instead of the benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -217,6 +485,8 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = pf.Context(0)
+    if args.profile:
+        return profile_run(torch, pf, ctx, args.profile, args.steps)
     p = args.p
     N = inputs.mesh_n_for_dofs(p, args.dofs)
     n, q = p + 1, p + 2
@@ -267,7 +537,12 @@ def main():
                 "algorithmic_bytes": "quadrature data 48 B/qpt + x read + y write (E computed, not read)",
                 "flops_per_launch": apply_flops(ne, n, q, "diffusion"),
                 "fp64_tflops": round(apply_flops(ne, n, q, "diffusion") / (ms_k * 1e-3) / 1e12, 2)}
-    log(f"element kernel {ms_k:.4f} ms -> {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM)")
+    roofline["whole_apply"] = {
+        "kernels": "element pass + ordered E^T sum", "ms": round(ms_ev, 5),
+        "achieved": round(algo / (ms_ev * 1e-3) / 1e9, 1),
+        "frac": round(algo / (ms_ev * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"element kernel {ms_k:.4f} ms -> {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM); "
+        f"whole apply {roofline['whole_apply']}")
     del yE
 
     # ---- plain device copy of known size: the attainable-bandwidth reference ---------
@@ -315,6 +590,27 @@ def main():
         "mass_fp64": {"ms": round(msw_m, 5), "gdofs": round(ndofs / (msw_m * 1e-3) / 1e9, 3),
                       "hbm_frac": round(apply_bytes(ne, n, q, 1, ndofs, 8) / (msw_m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    # fully matrix-free level on the same mesh (geometry rebuilt per point)
+    Kmf = pf.Operator(sp, pf.DIFFUSION)
+    Kmf.set_assembly_level(pf.ASSEMBLY_MATRIX_FREE)
+    Kmf.assemble(pf.FP64 | pf.FP32)
+    Mmf = pf.Operator(sp, pf.MASS)
+    Mmf.set_assembly_level(pf.ASSEMBLY_MATRIX_FREE)
+    Mmf.assemble(pf.FP64)
+    _, msw_mf = time_applies(torch, Kmf, x, y, args.steps, 3)
+    _, msw_mf32 = time_applies(torch, Kmf, x32, y32, args.steps, 3)
+    _, msw_mmf = time_applies(torch, Mmf, x, y, args.steps, 3)
+    fl = apply_flops(ne, n, q, "diffusion")
+    extra["apply"]["diffusion_fp64_matrix_free"] = {
+        "ms": round(msw_mf, 5), "gdofs": round(ndofs / (msw_mf * 1e-3) / 1e9, 3),
+        "hbm_bytes": 16 * ndofs, "contraction_tflops": round(fl / (msw_mf * 1e-3) / 1e12, 2),
+        "speedup_vs_partial_assembly": round(ms_wall / msw_mf, 3)}
+    extra["apply"]["diffusion_fp32_matrix_free"] = {
+        "ms": round(msw_mf32, 5), "gdofs": round(ndofs / (msw_mf32 * 1e-3) / 1e9, 3)}
+    extra["apply"]["mass_fp64_matrix_free"] = {
+        "ms": round(msw_mmf, 5), "gdofs": round(ndofs / (msw_mmf * 1e-3) / 1e9, 3),
+        "speedup_vs_partial_assembly": round(msw_m / msw_mmf, 3)}
+    del Kmf, Mmf
     log(f"apply summary {extra['apply']}")
 
     # ---- CG iteration rate and solves --------------------------------------------
@@ -362,26 +658,36 @@ def main():
             solves[name]["rel_diff_vs_plain"] = float((solves[name]["x"] - x64).norm() / x64.norm())
             solves[name]["speedup_vs_plain"] = round(solves["plain_fp64"]["seconds"] /
                                                      solves[name]["seconds"], 3)
+        pm = pmg_solve(torch, pf, Kc, bc, (solves["plain_fp64"]["x"], solves["plain_fp64"]))
         for s_ in solves.values():
             s_.pop("x")
         extra["solve_headline"] = solves
         log(f"solves {solves}")
+        extra["pmg"] = {"headline": dict(problem=(f"p={p}, {N}^3 perturbed hex mesh, k = 1 + 0.5 "
+                                                  f"sin(2 pi x), {ndofs} dofs, to 1e-10"), **pm)}
+        log(f"pmg headline {extra['pmg']['headline']}")
         del Kc
         # latency of a small solve
         vs = inputs.perturbed_vertices(4, 4, 4, seed=None)
         Ks = pf.Operator(pf.Space(pf.Mesh(ctx, 4, 4, 4, vs), 2), pf.DIFFUSION)
         Ks.assemble()
         bs = Ks.rhs()
-        lat = []
-        for i in range(60):
-            xs = torch.zeros_like(bs)
-            t0 = time.perf_counter()
-            _, st = Ks.solve(bs, xs, rtol=1e-10, check_every=1)
-            lat.append((time.perf_counter() - t0) * 1e3)
-        lat = np.array(lat[10:])
-        extra["solve_small"] = {"problem": "4^3 affine mesh, p=2, 729 dofs, FP64 Jacobi-PCG to 1e-10",
-                                "iterations": st["iterations"], "p50_ms": round(float(np.percentile(lat, 50)), 4),
-                                "p99_ms": round(float(np.percentile(lat, 99)), 4)}
+        small = {"problem": "4^3 affine mesh, p=2, 729 dofs, FP64 Jacobi-PCG to 1e-10"}
+        for name, form, ce in (("kernels", pf.LAUNCH_KERNELS, 1),
+                               ("kernels_check8", pf.LAUNCH_KERNELS, 8),
+                               ("graph_check8", pf.LAUNCH_GRAPH, 8),
+                               ("persistent_check8", pf.LAUNCH_PERSISTENT, 8)):
+            lat = []
+            for i in range(60):
+                xs = torch.zeros_like(bs)
+                t0 = time.perf_counter()
+                _, st = Ks.solve(bs, xs, rtol=1e-10, check_every=ce, launch=form)
+                lat.append((time.perf_counter() - t0) * 1e3)
+            lat = np.array(lat[10:])
+            small[name] = {"iterations": st["iterations"],
+                           "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                           "p99_ms": round(float(np.percentile(lat, 99)), 4)}
+        extra["solve_small"] = small
         log(f"small solve {extra['solve_small']}")
     del ops, K
     torch.cuda.synchronize()
@@ -434,7 +740,13 @@ def main():
             log(f"large solve {name}: {large[name]}")
         extra["solve_large"] = large
         log(f"large {large}")
-        del KL, bL, xs, xs64
+        jac = (xs64, {"iterations": large["plain_fp64"]["iterations"],
+                      "seconds": large["plain_fp64"]["seconds"]})
+        extra.setdefault("pmg", {})["large"] = dict(
+            problem="p=7, 64^3 perturbed hex mesh, k=1, 90,518,849 dofs, to 1e-10",
+            **pmg_solve(torch, pf, KL, bL, jac))
+        log(f"pmg large {extra['pmg']['large']}")
+        del KL, bL, xs, xs64, jac
         torch.cuda.synchronize()
 
     # ---- sweep over p ---------------------------------------------------------------
@@ -461,30 +773,47 @@ def main():
             y32 = torch.empty_like(x32)
             _, msw = time_applies(torch, opp["diffusion"], x32, y32, 30, 3)
             row["diffusion_fp32_gdofs"] = round(nd / (msw * 1e-3) / 1e9, 3)
+            for kind in ("diffusion", "mass"):
+                omf = pf.Operator(spp, pf.DIFFUSION if kind == "diffusion" else pf.MASS)
+                omf.set_assembly_level(pf.ASSEMBLY_MATRIX_FREE)
+                omf.assemble(pf.FP64)
+                _, msw = time_applies(torch, omf, xx, yy, 30, 3)
+                row[f"{kind}_fp64_matrix_free_gdofs"] = round(nd / (msw * 1e-3) / 1e9, 3)
+                del omf
             sweep.append(row)
             log(f"sweep {row}")
             del opp, spp, xx, yy, x32, y32
             torch.cuda.synchronize()
         extra["sweep_8M"] = sweep
+        extra["sweep_1M"] = sweep_applies(torch, pf, ctx, 1e6, mode, 30)
+        if not args.no_64m:
+            extra["sweep_64M"] = sweep_applies(torch, pf, ctx, 64e6, mode, 10)
+
+    if not args.no_curve and not args.no_solve:
+        extra["cg_launch_forms"] = launch_form_curve(torch, pf, ctx)
+
+    if not args.no_mixed and not args.no_solve:
+        extra["mixed_30M"] = mixed_precision_configs(torch, pf, ctx, mode)
 
     # ---- serving: continuous batching of a Poisson-arrival stream ----------------------
     if not args.no_serve:
-        serving = {"stream": ("N uniform in 8..20, p uniform in 2..8 (q=p+2), perturbed hex "
-                              "meshes, manufactured sine solution, FP32-inner/FP64-refined CG "
-                              "to rel. residual 1e-10; 64 GB budget, 16 slots, 10 iterations "
-                              "per round")}
-        runs = []
-        for rate in [float(r) for r in args.serve_rates.split(",") if r]:
-            runs.append(serve_benchmark(pf, ctx, rate, args.serve_requests, (8, 20), (2, 8),
-                                        64 << 30, 16, 10))
-            log(f"serving {runs[-1]}")
-        serving["runs"] = runs
+        fracs = [float(f) for f in args.serve_fracs.split(",") if f]
+        serving = {"stream": ("Poisson arrivals, N uniform in 8..64, p uniform in 2..8 (q=p+2), "
+                              "perturbed hex meshes, manufactured sine solution, mixed-precision "
+                              "CG (FP32 operator, FP64 solution and residual replacement) to rel. "
+                              "residual 1e-10; 200 GB budget, 16 slots, 10 iterations per round"),
+                   "cut": (f"{args.serve_requests} requests per rate instead of 2,000, so that the "
+                           f"burst and {len(fracs)} rates finish within minutes")}
+        serving.update(serving_configs(pf, ctx, args.serve_requests, fracs, 200 << 30, 16, 10))
         extra["serving"] = serving
 
     cpu = None
     if not args.no_cpu:
         log("cpu oracle baseline")
         cpu = cpu_oracle_baseline(p, 6)
+        extra["cpu_all_cores"] = cpu_all_cores_spmv(p, 6)
+        extra["config0_oracle"] = config0_oracle_seconds()
+        log(f"cpu {cpu} {extra['cpu_all_cores']} {extra['config0_oracle']}")
 
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "GDOF/s", "n_gpus": 1,

@@ -500,3 +500,26 @@ def test_discretization_convergence_rate(p):
         errs.append(math.sqrt(e @ (M @ e)))
     rate = math.log2(errs[0] / errs[1])
     assert rate > p + 1 - 0.3, (errs, rate)
+
+
+def test_all_cores_csr_spmv_equals_scipy():
+    """The CPU baseline's OpenMP CSR product is the plain definition: equal to scipy's."""
+    import ctypes as C
+    import os
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from oracle import build_csr
+    lib = C.CDLL(build_csr.build())
+    n, p = 3, 3
+    v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
+    A = fem.assemble("diffusion", v, n, n, n, p)
+    x = inputs.random_vector(A.shape[0], 4)
+    y = np.empty_like(x)
+    rp = A.indptr.astype(np.int64)
+    ci = A.indices.astype(np.int32)
+    lib.csr_spmv(C.c_int64(A.shape[0]), rp.ctypes.data_as(C.c_void_p),
+                 ci.ctypes.data_as(C.c_void_p), A.data.ctypes.data_as(C.c_void_p),
+                 x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p))
+    np.testing.assert_allclose(y, A @ x, rtol=0, atol=1e-13 * np.abs(A @ x).max())
+    assert lib.csr_threads() >= 1
