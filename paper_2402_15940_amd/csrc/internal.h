@@ -512,6 +512,10 @@ hipError_t launch_power_next(double* v, const double* w, const double* dinv, dou
 
 // Up to `iters` FP64 Jacobi-PCG iterations in one cooperative persistent
 // launch (k_persistent.hip); *grid receives the workgroup count (<= max_blocks).
+// bar points to kPersistentBarrierBytes of barrier words whose arrival
+// counters are zero on entry (and again on return; the generations may hold
+// anything).
+constexpr size_t kPersistentBarrierBytes = 18 * 128;
 hipError_t launch_pcg_persistent(int kind, int p, const ApplyArgs<double>& a, int64_t groups,
                                  double* xs, double* r, const double* dinv, double* bpart,
                                  double* npart, CgState* st, void* bar, int* err,

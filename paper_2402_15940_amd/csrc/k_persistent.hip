@@ -9,9 +9,9 @@
 // expression, so the same bits, in both phases):
 //   1. the element pass of A p_k (the same device code as the separate
 //      kernel, with the direction formed at its gather: x-interleaved E-vector
-//      and per-element-group partials of p . A p), each workgroup walking
-//      element groups b, b + G, b + 2G, ...; its partials are summed per
-//      workgroup in that order;
+//      and per-element-group partials of p . A p), each workgroup walking its
+//      share of the element groups in a fixed order (one contiguous range per
+//      XCD); its partials are summed per workgroup in that order;
 //   2. every workgroup sums the G workgroup partials in the same fixed order
 //      (so every workgroup holds the same alpha), then the ordered E^T sum of
 //      its node chunks with p = p_k stored, x += alpha p_k, r -= alpha A p_k
@@ -37,10 +37,18 @@ using vec::xrows_geom;
 using vec::xrows_load;
 using vec::xrows_sum;
 
+// Barrier words, each on its own 128-byte line: one arrival counter and one
+// generation per group of workgroups (workgroup b in group b mod ngroups,
+// ngroups = min(G, 8), so with the round-robin dealing a group is one XCD's
+// workgroups), and a root counter and generation over the groups.
+constexpr int kLine = 32;  // unsigned words per 128-byte line
 struct PcgBarrier {
-  unsigned count;
-  unsigned gen;
+  unsigned count[8 * kLine];
+  unsigned gen[8 * kLine];
+  unsigned root_count[kLine];
+  unsigned root_gen[kLine];
 };
+static_assert(sizeof(PcgBarrier) == kPersistentBarrierBytes, "barrier words");
 
 template <typename T>
 struct PcgArgs {
@@ -59,37 +67,88 @@ struct PcgArgs {
   int64_t groups;
 };
 
-// Grid-wide barrier: arrival counter and generation word; bounded wait.
+// Bounded wait until *w differs from `seen`; false (and the error flag set)
+// when the spin limit is reached.
+__device__ __forceinline__ bool wait_change(const unsigned* w, unsigned seen, long long spin_limit,
+                                            int* err) {
+  long long k = 0;
+  while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seen) {
+    if (++k > spin_limit) {
+      atomicOr(err, 1);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  return true;
+}
+
+// Grid-wide barrier in two levels: the last workgroup to arrive in its group
+// arrives at the root; the last group to arrive advances the root generation;
+// each group's last arriver, once it sees that, advances its group's
+// generation, which the rest of the group waits on.  So at most eight
+// workgroups poll the root and the others spread over eight words.  Release
+// fences before each arrival and acquire fences after each observed
+// generation carry every workgroup's writes to every other.  Every wait is
+// bounded; a workgroup whose wait runs out sets the error flag and reports
+// false, and those waiting on it run out the same way.
 __device__ __forceinline__ bool grid_barrier(PcgBarrier* bar, unsigned nblocks,
                                              long long spin_limit, int* err) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    ok = 1;
-    const unsigned gen = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // this workgroup's writes (and the generation read) before the arrival
+    const unsigned ng = nblocks < 8u ? nblocks : 8u;
+    const unsigned grp = blockIdx.x % ng;
+    const unsigned members = (nblocks - grp + ng - 1) / ng;
+    unsigned* cnt = &bar->count[grp * kLine];
+    unsigned* gen = &bar->gen[grp * kLine];
+    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned arrived = atomicAdd(&bar->count, 1u);
-    if (arrived == nblocks - 1) {
-      atomicExch(&bar->count, 0u);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      atomicAdd(&bar->gen, 1u);
-    } else {
-      long long k = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (++k > spin_limit) {
-          atomicOr(err, 1);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+    bool good = true;
+    if (atomicAdd(cnt, 1u) == members - 1) {
+      // last of the group: the others' writes, then arrival at the root
+      atomicExch(cnt, 0u);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      const unsigned r0 =
+          __hip_atomic_load(bar->root_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (atomicAdd(bar->root_count, 1u) == ng - 1) {
+        atomicExch(bar->root_count, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        atomicAdd(bar->root_gen, 1u);
+      } else {
+        good = wait_change(bar->root_gen, r0, spin_limit, err);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
       }
+      atomicAdd(gen, 1u);  // release the group (also when the wait ran out)
+    } else {
+      good = wait_change(gen, g0, spin_limit, err);
     }
-    // the other workgroups' writes before their arrival
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = good ? 1 : 0;
   }
   __syncthreads();
   return ok != 0;
+}
+
+#ifndef PAFEM_PCG_PHASE2_NODES
+#define PAFEM_PCG_PHASE2_NODES 2
+#endif
+constexpr int kPhase2Nodes = PAFEM_PCG_PHASE2_NODES;
+
+// The items [0, total) a workgroup walks.  Workgroups are dealt to the XCDs
+// round-robin; each XCD takes one contiguous range of items, walked by its
+// workgroups in turn (neighbouring element groups share face dofs in that
+// XCD's L2).  With fewer workgroups than XCDs, a plain strided walk.
+struct Walk {
+  int64_t first, end, stride;
+};
+__device__ __forceinline__ Walk xcd_walk(int64_t b, int64_t G, int64_t total) {
+  using apply::kXcds;
+  if (G < kXcds) return {b, total, G};
+  const int64_t x = b % kXcds, l = b / kXcds;
+  const int64_t gx = (G - x + kXcds - 1) / kXcds;  // workgroups on XCD x (>= 1)
+  const int64_t q = total / kXcds, r = total % kXcds;
+  const int64_t start = x * q + (x < r ? x : r);
+  return {start + l, start + q + (x < r ? 1 : 0), gx};
 }
 
 // Sum over the workgroup of NV values per thread, returned to every thread.
@@ -119,7 +178,10 @@ template <int P, typename T, int KIND>
 __global__ __launch_bounds__((Cfg<P, P + 2, T, KIND>::THREADS), 2) void k_pcg_persistent(
     PcgArgs<T> pa) {
   using C = Cfg<P, P + 2, T, KIND>;
-  constexpr int NT = C::THREADS, R = kXRowsNodes;
+  // phase 2 takes R nodes per thread at a time, all their loads issued before
+  // the first use (few waves per SIMD fit next to the element pass, so each
+  // keeps several loads in flight)
+  constexpr int NT = C::THREADS, R = kPhase2Nodes;
   __shared__ T smem[C::NE * C::L];
   const unsigned G = gridDim.x;
   const int tid = threadIdx.x;
@@ -129,11 +191,13 @@ __global__ __launch_bounds__((Cfg<P, P + 2, T, KIND>::THREADS), 2) void k_pcg_pe
   int iter = pa.st->iter, done = pa.st->done;
   const int maxit = pa.st->maxit;
   T* p = const_cast<T*>(pa.a.x);
+  const Walk wg = xcd_walk(blockIdx.x, G, pa.groups);
+  const Walk wn = xcd_walk(blockIdx.x, G, (g.n + NT * R - 1) / (NT * R));
   for (int it = 0; it < pa.iters && !done; ++it) {
     const T beta_t = (T)beta;
     // ---- 1: element pass of A p_k, p_k = dinv r + beta p formed at the gather ----
     double mine = 0.0;  // this workgroup's groups, in walking order (thread 0)
-    for (int64_t grp = blockIdx.x; grp < pa.groups; grp += G) {
+    for (int64_t grp = wg.first; grp < wg.end; grp += wg.stride) {
       if constexpr (KIND == PAFEM_DIFFUSION)
         apply::diff_elements<P, P + 2, T, kScatterXRowsDot, PAFEM_INDEX_LATTICE, C::NE, false,
                              false, true>(pa.a, grp * C::NE, smem, tid, beta_t);
@@ -155,9 +219,10 @@ __global__ __launch_bounds__((Cfg<P, P + 2, T, KIND>::THREADS), 2) void k_pcg_pe
     alpha = rz / pAp;
     double v2[2] = {0.0, 0.0};
     const T alpha_t = (T)alpha;
-    for (int64_t base = (int64_t)blockIdx.x * (NT * R) + tid; base - tid < g.n;
-         base += (int64_t)G * (NT * R)) {
+    for (int64_t c = wn.first; c < wn.end; c += wn.stride) {
+      const int64_t base = c * (NT * R) + tid;
       XRowsLoads<T> L[R];
+      T dv[R], rv[R], pv[R], xv[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int64_t iq = base + q * NT;
@@ -165,15 +230,24 @@ __global__ __launch_bounds__((Cfg<P, P + 2, T, KIND>::THREADS), 2) void k_pcg_pe
       }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
+        const int64_t iq = base + q * NT;
+        const int64_t ic = iq < g.n ? iq : g.n - 1;
+        dv[q] = pa.dinv[ic];
+        rv[q] = pa.r[ic];
+        pv[q] = p[ic];
+        xv[q] = pa.xs[ic];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
         const int64_t i = base + q * NT;
         if (i >= g.n) break;
-        const T pi = pa.dinv[i] * pa.r[i] + beta_t * p[i];
+        const T pi = dv[q] * rv[q] + beta_t * pv[q];
         p[i] = pi;
         const T acc = L[q].ess ? pi : xrows_sum(L[q]);
-        pa.xs[i] += alpha_t * pi;
-        const T ri = pa.r[i] - alpha_t * acc;
+        pa.xs[i] = xv[q] + alpha_t * pi;
+        const T ri = rv[q] - alpha_t * acc;
         pa.r[i] = ri;
-        const T zi = pa.dinv[i] * ri;
+        const T zi = dv[q] * ri;
         v2[0] += (double)ri * (double)zi;
         v2[1] += (double)ri * (double)ri;
       }
@@ -251,7 +325,8 @@ hipError_t launch_kind(int p, const PcgArgs<T>& pa, int max_blocks, int* grid, h
 // Up to `iters` FP64 Jacobi-PCG iterations in one cooperative launch.  a is
 // the element-pass argument block (x = direction, yE = E-vector, dot_part =
 // one partial per element group); bpart and npart hold at least max_blocks
-// and 2 max_blocks doubles; bar (two words) is zero on entry and on return.
+// and 2 max_blocks doubles; bar holds kPersistentBarrierBytes whose arrival
+// counters are zero on entry and on return.
 hipError_t launch_pcg_persistent(int kind, int p, const ApplyArgs<double>& a, int64_t groups,
                                  double* xs, double* r, const double* dinv, double* bpart,
                                  double* npart, CgState* st, void* bar, int* err,

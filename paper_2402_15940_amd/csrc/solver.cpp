@@ -186,12 +186,15 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
       int64_t groups = 0;
       PAFEM_TRY(cg_element_args(op, p, &a, &groups));
       constexpr int kMaxPersistentBlocks = 8192;
-      PAFEM_TRY(op->d_pers.ensure((3 * (size_t)kMaxPersistentBlocks + 16) * sizeof(double)));
+      // partials, then the barrier words and the error flag (zero on entry)
+      constexpr size_t kBarDoubles = kPersistentBarrierBytes / sizeof(double) + 16;
+      PAFEM_TRY(op->d_pers.ensure((3 * (size_t)kMaxPersistentBlocks + kBarDoubles) *
+                                  sizeof(double)));
       double* bpart = op->d_pers.as<double>();
       double* npart = bpart + kMaxPersistentBlocks;
       void* bar = npart + 2 * kMaxPersistentBlocks;
-      int* err = reinterpret_cast<int*>(static_cast<double*>(bar) + 1);
-      PAFEM_TRY_HIP(hipMemsetAsync(bar, 0, 2 * sizeof(double), s));
+      int* err = reinterpret_cast<int*>(static_cast<double*>(bar) + kBarDoubles - 16);
+      PAFEM_TRY_HIP(hipMemsetAsync(bar, 0, kBarDoubles * sizeof(double), s));
       for (;;) {
         int grid = 0;
         PAFEM_TRY_HIP(launch_pcg_persistent(op->kind, sp->p, a, groups, x, r, dinv, bpart, npart,
