@@ -155,9 +155,14 @@ int pafem_basis_tables(int p, int q, double* gll_nodes, double* gl_points, doubl
 /* Defined by: the operator decomposition figure (A = P^T G^T B^T D B G P) for
  * the mass and diffusion forms (the paper's BP1 and BP3 benchmarks, section
  * "State-of-the-art performance on exascale platforms and AMD GPUs").
- * Create a MASS or DIFFUSION operator on `space` with q1d points per direction
- * (0 = default p+2; any other value but p+2 gives UNSUPPORTED).  The
- * coefficient defaults to the constant 1.  Nothing is computed until
+ * Create a MASS or DIFFUSION operator on `space` with q1d Gauss-Legendre
+ * points per direction: 0 = the default p+2, or any p+1 <= q1d <= 10
+ * (others give UNSUPPORTED).  The default runs the tuned element kernels and
+ * every solve and launch form; another q1d runs a run-time-sized element
+ * kernel (plain sum factorization through LDS, one workgroup per element),
+ * and then bfloat16 quadrature data, the matrix-free level and the persistent
+ * launch form give UNSUPPORTED, and CG runs its separate-kernel iteration.
+ * The coefficient defaults to the constant 1.  Nothing is computed until
  * pafem_op_assemble. */
 int pafem_op_create(pafem_space* space, int kind, int q1d, pafem_op** out);
 int pafem_op_destroy(pafem_op* op);

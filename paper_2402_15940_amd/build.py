@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 SOURCES = ["host_setup.cpp", "api.cpp", "solver.cpp", "server.cpp", "k_setup.hip", "k_apply.hip",
            "k_vec.hip", "k_batched.hip", "noalloc.hip", "pmg.cpp",
-           "k_transfer.hip", "k_persistent.hip"]
+           "k_transfer.hip", "k_persistent.hip", "k_generic.hip"]
 
 ARCH = os.environ.get("PAFEM_ARCH", "gfx950")
 

@@ -548,8 +548,8 @@ int pafem_op_create(pafem_space* space, int kind, int q1d, pafem_op** out) {
   CHECK_ARG(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, "kind must be MASS or DIFFUSION");
   const int p = space->p;
   const int q = q1d == 0 ? p + 2 : q1d;
-  if (q != p + 2) {
-    set_error("only q1d = p + 2 is supported");
+  if (q < p + 1 || q > kMaxQ1d) {
+    set_error("q1d must be 0 (p + 2) or within p + 1 .. 10");
     return PAFEM_ERR_UNSUPPORTED;
   }
   PAFEM_TRY(need_device(space->mesh->ctx));
@@ -657,6 +657,10 @@ int pafem_op_assemble(pafem_op* op, int prec_mask, void* stream) {
   CHECK_ARG((prec_mask & ~(PAFEM_FP64 | PAFEM_FP32 | PAFEM_BF16)) == 0, "unknown precision bits");
   PAFEM_TRY(need_device(op->space->mesh->ctx));
   const bool mf = op->level == PAFEM_ASSEMBLY_MATRIX_FREE;
+  if ((prec_mask & PAFEM_BF16) && op->q != op->space->p + 2) {
+    set_error("bfloat16 quadrature data needs the default q1d = p + 2");
+    return PAFEM_ERR_UNSUPPORTED;
+  }
   if (mf) {
     CHECK_ARG((prec_mask & PAFEM_BF16) == 0,
               "a matrix-free operator stores no quadrature data to round to bfloat16");
@@ -723,6 +727,10 @@ int pafem_op_set_assembly_level(pafem_op* op, int level) {
     CHECK_ARG(op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC &&
                   op->index_mode == PAFEM_INDEX_LATTICE,
               "the matrix-free level runs the deterministic E^T on the lattice numbering");
+    if (op->q != op->space->p + 2) {
+      set_error("the matrix-free level needs the default q1d = p + 2");
+      return PAFEM_ERR_UNSUPPORTED;
+    }
   }
   if (level != op->level) {
     op->level = level;

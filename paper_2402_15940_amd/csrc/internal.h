@@ -69,6 +69,7 @@ struct DevBuf {
 // host-side setup (basis.cpp, mesh.cpp)
 // ---------------------------------------------------------------------------
 constexpr int kMaxP = 8;
+constexpr int kMaxQ1d = 10;  // largest quadrature size per direction
 constexpr int kMaxQ = 12;
 
 // Gauss-Lobatto-Legendre nodes on [0,1] (p+1 of them), by Newton's method on the
@@ -339,9 +340,15 @@ __host__ __device__ __forceinline__ int xrows_index(int nx, int ny, int n, int e
 }
 
 // y (atomic) or yE (deterministic) from one fused sum-factorized element pass.
+// q = p + 2 runs the tuned kernels; p + 1 <= q <= kMaxQ1d otherwise runs the
+// run-time-sized kernel (k_generic.hip: atomic, element-major or
+// x-interleaved output; no bfloat16 data, no matrix-free level, no CG dot).
 template <typename T>
 hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode,
                         const ApplyArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_apply_generic(int kind, int p, int q, int scatter_mode, const ApplyArgs<T>& a,
+                                hipStream_t s);
 
 // Element-diagonal (E-vector) by sum factorization.
 hipError_t launch_diag_elem(int kind, int p, int q, const double* qd, const double* B,

@@ -97,7 +97,14 @@ hipError_t apply_p(int kind, int scatter, int idx, const ApplyArgs<T>& a, hipStr
 template <typename T>
 hipError_t launch_apply(int kind, int p, int q, int scatter_mode, int index_mode,
                         const ApplyArgs<T>& a, hipStream_t s) {
-  if (q != p + 2) return hipErrorInvalidValue;
+  if (q != p + 2) {
+    // a non-default quadrature size: the run-time-sized kernel (its lattice
+    // numbering equals the stored maps, so either E^T follows it)
+    if (index_mode == PAFEM_INDEX_MAP && scatter_mode != PAFEM_SCATTER_ATOMIC &&
+        scatter_mode != kScatterEvector)
+      return hipErrorInvalidValue;
+    return launch_apply_generic<T>(kind, p, q, scatter_mode, a, s);
+  }
   const bool xrows = scatter_mode == kScatterXRows || scatter_mode == kScatterXRowsDot;
   if (scatter_mode != PAFEM_SCATTER_ATOMIC && scatter_mode != kScatterEvector && !xrows)
     return hipErrorInvalidValue;

@@ -277,27 +277,37 @@ __global__ __launch_bounds__(Q * Q) void k_rhs_elem(GeomArgs g, const double* __
 }
 
 
-template <int P>
-hipError_t diag_p(int kind, const double* qd, const double* B, const double* G, int64_t ne,
+// Launches for order P and quadrature size q (P + 1 <= q <= kMaxQ1d), one
+// instantiation per q.
+template <int P, int Q = P + 1>
+hipError_t diag_p(int q, int kind, const double* qd, const double* B, const double* G, int64_t ne,
                   double* dE, hipStream_t s) {
-  constexpr int Q = P + 2;
-  if (ne == 0) return hipSuccess;
-  if (kind == PAFEM_DIFFUSION)
-    hipLaunchKernelGGL((k_diag_elem<P, Q, PAFEM_DIFFUSION>), dim3(ne), dim3(Q * Q), 0, s, qd, B,
-                       G, ne, dE);
-  else
-    hipLaunchKernelGGL((k_diag_elem<P, Q, PAFEM_MASS>), dim3(ne), dim3(Q * Q), 0, s, qd, B, G,
-                       ne, dE);
-  return hipGetLastError();
+  if constexpr (Q > kMaxQ1d) {
+    return hipErrorInvalidValue;
+  } else {
+    if (q != Q) return diag_p<P, Q + 1>(q, kind, qd, B, G, ne, dE, s);
+    if (ne == 0) return hipSuccess;
+    if (kind == PAFEM_DIFFUSION)
+      hipLaunchKernelGGL((k_diag_elem<P, Q, PAFEM_DIFFUSION>), dim3(ne), dim3(Q * Q), 0, s, qd, B,
+                         G, ne, dE);
+    else
+      hipLaunchKernelGGL((k_diag_elem<P, Q, PAFEM_MASS>), dim3(ne), dim3(Q * Q), 0, s, qd, B, G,
+                         ne, dE);
+    return hipGetLastError();
+  }
 }
 
-template <int P>
-hipError_t rhs_p(const GeomArgs& g, const double* B, const double* f_q, double* bE,
+template <int P, int Q = P + 1>
+hipError_t rhs_p(int q, const GeomArgs& g, const double* B, const double* f_q, double* bE,
                  hipStream_t s) {
-  constexpr int Q = P + 2;
-  if (g.ne == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rhs_elem<P, Q>), dim3(g.ne), dim3(Q * Q), 0, s, g, B, f_q, bE);
-  return hipGetLastError();
+  if constexpr (Q > kMaxQ1d) {
+    return hipErrorInvalidValue;
+  } else {
+    if (q != Q) return rhs_p<P, Q + 1>(q, g, B, f_q, bE, s);
+    if (g.ne == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_rhs_elem<P, Q>), dim3(g.ne), dim3(Q * Q), 0, s, g, B, f_q, bE);
+    return hipGetLastError();
+  }
 }
 
 }  // namespace
@@ -322,32 +332,30 @@ hipError_t launch_qpoint_coords(const GeomArgs& g, double* xyz, hipStream_t s) {
 
 hipError_t launch_diag_elem(int kind, int p, int q, const double* qd, const double* B,
                             const double* G, int64_t ne, double* dE, hipStream_t s) {
-  if (q != p + 2) return hipErrorInvalidValue;
   switch (p) {
-    case 1: return diag_p<1>(kind, qd, B, G, ne, dE, s);
-    case 2: return diag_p<2>(kind, qd, B, G, ne, dE, s);
-    case 3: return diag_p<3>(kind, qd, B, G, ne, dE, s);
-    case 4: return diag_p<4>(kind, qd, B, G, ne, dE, s);
-    case 5: return diag_p<5>(kind, qd, B, G, ne, dE, s);
-    case 6: return diag_p<6>(kind, qd, B, G, ne, dE, s);
-    case 7: return diag_p<7>(kind, qd, B, G, ne, dE, s);
-    case 8: return diag_p<8>(kind, qd, B, G, ne, dE, s);
+    case 1: return diag_p<1>(q, kind, qd, B, G, ne, dE, s);
+    case 2: return diag_p<2>(q, kind, qd, B, G, ne, dE, s);
+    case 3: return diag_p<3>(q, kind, qd, B, G, ne, dE, s);
+    case 4: return diag_p<4>(q, kind, qd, B, G, ne, dE, s);
+    case 5: return diag_p<5>(q, kind, qd, B, G, ne, dE, s);
+    case 6: return diag_p<6>(q, kind, qd, B, G, ne, dE, s);
+    case 7: return diag_p<7>(q, kind, qd, B, G, ne, dE, s);
+    case 8: return diag_p<8>(q, kind, qd, B, G, ne, dE, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_rhs_elem(const GeomArgs& g, int p, const double* B, const double* f_q,
                            double* bE, hipStream_t s) {
-  if (g.q != p + 2) return hipErrorInvalidValue;
   switch (p) {
-    case 1: return rhs_p<1>(g, B, f_q, bE, s);
-    case 2: return rhs_p<2>(g, B, f_q, bE, s);
-    case 3: return rhs_p<3>(g, B, f_q, bE, s);
-    case 4: return rhs_p<4>(g, B, f_q, bE, s);
-    case 5: return rhs_p<5>(g, B, f_q, bE, s);
-    case 6: return rhs_p<6>(g, B, f_q, bE, s);
-    case 7: return rhs_p<7>(g, B, f_q, bE, s);
-    case 8: return rhs_p<8>(g, B, f_q, bE, s);
+    case 1: return rhs_p<1>(g.q, g, B, f_q, bE, s);
+    case 2: return rhs_p<2>(g.q, g, B, f_q, bE, s);
+    case 3: return rhs_p<3>(g.q, g, B, f_q, bE, s);
+    case 4: return rhs_p<4>(g.q, g, B, f_q, bE, s);
+    case 5: return rhs_p<5>(g.q, g, B, f_q, bE, s);
+    case 6: return rhs_p<6>(g.q, g, B, f_q, bE, s);
+    case 7: return rhs_p<7>(g.q, g, B, f_q, bE, s);
+    case 8: return rhs_p<8>(g.q, g, B, f_q, bE, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -43,7 +43,8 @@ int ensure_partials(Op* op, int64_t n) {
 // forms p . A p per workgroup, and the ordered E^T sum applies the updates of
 // x and r and forms (r . z, r . r) without storing A p.
 bool fused_cg(const Op* op) {
-  return op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC && op->index_mode == PAFEM_INDEX_LATTICE;
+  return op->scatter_mode == PAFEM_SCATTER_DETERMINISTIC &&
+         op->index_mode == PAFEM_INDEX_LATTICE && op->q == op->space->p + 2;
 }
 
 // alpha, x += alpha p, r -= alpha A p, beta (the direction update follows).
@@ -423,8 +424,8 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
        (o->mode != PAFEM_SOLVE_PLAIN_FP64 || !fused_cg(op) ||
         op->level != PAFEM_ASSEMBLY_PARTIAL))) {
     set_error("launch form not available for this mode (graph: PLAIN_FP64 and IR; persistent: "
-              "PLAIN_FP64 with the deterministic E^T on the lattice numbering and stored "
-              "quadrature data)");
+              "PLAIN_FP64 with the deterministic E^T on the lattice numbering, stored "
+              "quadrature data and q = p + 2)");
     return PAFEM_ERR_INVALID_ARG;
   }
   if (mixed && !(o->inner_rtol > 0.0 && o->inner_rtol < 1.0)) {
