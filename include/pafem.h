@@ -310,6 +310,9 @@ typedef struct {
   double rel_res;       /* final relative residual of the last CG recursion */
   double true_rel_res;  /* ||b - A x||_2 / ||b||_2 recomputed in FP64 after the solve */
   double seconds;       /* wall time of the solve on the host clock */
+  int fp64_inner_solves; /* IR: inner solves run in FP64 because a reduced-precision one gave
+                            a non-finite result or cut the FP64 residual by less than a tenth
+                            (such a solve then continues in FP64) */
 } pafem_solve_stats;
 
 /* Defined by: section "Matrix-free solvers for high-order finite elements"

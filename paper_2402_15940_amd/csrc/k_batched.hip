@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_b_beta(const BatchEntry<T>* _
     st->rz = r[0];
     st->rr = r[1];
     st->iter += 1;
-    if (r[1] <= st->rr_stop || st->iter >= st->maxit)
+    if (r[1] <= st->rr_stop || st->iter >= st->maxit || !isfinite(r[1]))
       st->done = 1;
     else if (st->delta2 > 0.0 && r[1] <= st->delta2 * st->rr_ref)
       st->done = 2;  // mixed CG: pause for a residual replacement

@@ -270,7 +270,7 @@ __global__ __launch_bounds__((Cfg<P, P + 2, T, KIND>::THREADS), 2) void k_pcg_pe
       rr = v[1];
     }
     iter += 1;
-    done = (rr <= rr_stop || iter >= maxit) ? 1 : 0;
+    done = (rr <= rr_stop || iter >= maxit || !isfinite(rr)) ? 1 : 0;
   }
   if (blockIdx.x == 0 && tid == 0) {
     pa.st->rz = rz;

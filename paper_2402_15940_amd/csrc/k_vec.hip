@@ -312,7 +312,8 @@ __global__ void k_cg_beta(const double* __restrict__ partials, int nb, CgState* 
     st->rz = r[0];
     st->rr = r[1];
     st->iter += 1;
-    if (r[1] <= st->rr_stop || st->iter >= st->maxit)
+    // a residual that overflowed or became NaN ends the iteration (not converged)
+    if (r[1] <= st->rr_stop || st->iter >= st->maxit || !isfinite(r[1]))
       st->done = 1;
     else if (st->delta2 > 0.0 && r[1] <= st->delta2 * st->rr_ref)
       st->done = 2;  // the recursive residual fell by delta: replace it by the true one
@@ -367,7 +368,7 @@ __global__ void k_replace_final(const double* __restrict__ partials, int nb, CgS
     st->rz = r[0];
     st->rr = r[1];
     st->rr_ref = r[1];
-    st->done = (r[1] <= st->rr_stop || st->iter >= st->maxit) ? 1 : 0;
+    st->done = (r[1] <= st->rr_stop || st->iter >= st->maxit || !isfinite(r[1])) ? 1 : 0;
   }
 }
 

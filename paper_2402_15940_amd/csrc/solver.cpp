@@ -10,6 +10,7 @@
 // partials, beta, direction update).  The host reads the state
 // every `check_every` iterations; kernels of iterations enqueued after
 // convergence see state.done and return at once.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -141,6 +142,10 @@ int cg_graph(Op* op, T* x, T* r, T* p, T* Ap, const T* dinv, double* part, CgSta
 // Spin limit of the persistent kernel's barrier waits (each poll sleeps
 // briefly): far beyond any legitimate wait, so that a stall ends the launch.
 constexpr long long kSpinLimit = 1LL << 24;
+
+// Defect correction: an FP32/BF16 correction must bring the FP64 residual
+// below this fraction of its value before it, or the inner solves switch to FP64.
+constexpr double kIrStagnation = 0.9;
 
 template <typename T>
 int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T* dinv,
@@ -527,9 +532,10 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     // r = b - A x (FP64)
     PAFEM_TRY(apply_impl<double>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));
     PAFEM_TRY_HIP(launch_residual(b, Ap, r, n, s));
-    int total_inner = 0, outer = 0;
-    double rel = 0.0;
-    bool ok = false;
+    int total_inner = 0, outer = 0, n64 = 0;
+    double rel = 0.0, rel_prev = 0.0;
+    bool ok = false, use64 = false, after32 = false;
+    const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-4;
     for (;;) {
       PAFEM_TRY_HIP(launch_dot_partial<double>(r, r, n, part, nb, nullptr, s));
       PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, rr_dev, s));
@@ -541,22 +547,44 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
         ok = true;
         break;
       }
-      if (outer >= o->max_outer) break;
-      // inner FP32 solve of A d = r / ||r||
-      PAFEM_TRY_HIP(launch_scale_to_f32(r, rr_dev, r32, n, s));
-      CgResult res;
-      // the inner solve overwrites the partials; keep ||r||^2 in its own slot
-      PAFEM_TRY(run_pcg<float>(op, r32, d32, true, r32, p32, Ap32, op->d_dinv32.as<float>(),
-                               o->inner_rtol > 0 ? o->inner_rtol : 1e-4, o->maxit,
-                               o->check_every, s, res,
-                               o->mode == PAFEM_SOLVE_IR_BF16 ? PAFEM_BF16 : PAFEM_FP32,
-                               o->launch));
-      total_inner += res.iterations;
-      PAFEM_TRY_HIP(launch_axpy_from_f32(x, rr_dev, d32, n, s));
+      if (!std::isfinite(rel) || outer >= o->max_outer) break;
+      // a reduced-precision correction that did not reduce the FP64 residual
+      // by a tenth: the inner solves continue in FP64
+      if (after32 && !(rel <= kIrStagnation * rel_prev)) use64 = true;
+      rel_prev = rel;
+      after32 = false;
+      if (!use64) {
+        // inner FP32 solve of A d = r / ||r||
+        PAFEM_TRY_HIP(launch_scale_to_f32(r, rr_dev, r32, n, s));
+        CgResult res;
+        // the inner solve overwrites the partials; keep ||r||^2 in its own slot
+        PAFEM_TRY(run_pcg<float>(op, r32, d32, true, r32, p32, Ap32, op->d_dinv32.as<float>(),
+                                 inner_rtol, o->maxit, o->check_every, s, res,
+                                 o->mode == PAFEM_SOLVE_IR_BF16 ? PAFEM_BF16 : PAFEM_FP32,
+                                 o->launch));
+        total_inner += res.iterations;
+        if (std::isfinite(res.rr)) {
+          PAFEM_TRY_HIP(launch_axpy_from_f32(x, rr_dev, d32, n, s));
+          after32 = true;
+        } else {
+          use64 = true;  // overflow or NaN in reduced precision: discard the correction
+        }
+      }
+      if (use64) {
+        // FP64 inner solve: CG from the current x, reducing the residual by
+        // inner_rtol (not beyond rtol / 2)
+        CgResult res;
+        const double target = std::max(rel * inner_rtol, 0.5 * o->rtol);
+        PAFEM_TRY(run_pcg<double>(op, b, x, false, r, p, Ap, op->d_dinv64.as<double>(), target,
+                                  o->maxit, o->check_every, s, res));
+        total_inner += res.iterations;
+        ++n64;
+      }
       PAFEM_TRY(apply_impl<double>(op, x, Ap, PAFEM_APPLY_CONSTRAINED, nullptr, s));
       PAFEM_TRY_HIP(launch_residual(b, Ap, r, n, s));
       ++outer;
     }
+    stats->fp64_inner_solves = n64;
     stats->iterations = total_inner;
     stats->outer_iterations = outer;
     stats->rel_res = rel;

@@ -58,7 +58,8 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int), ("rel_res", C.c_double),
-                ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+                ("true_rel_res", C.c_double), ("seconds", C.c_double),
+                ("fp64_inner_solves", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
