@@ -461,12 +461,12 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the p=7 64^3 (90M dofs) single solve")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-fracs", type=str, default="0.5,1.1",
+    ap.add_argument("--serve-fracs", type=str, default="0.25,0.5,0.9,1.1",
                     help="arrival rates of the serving stream as fractions of its measured capacity "
                          "(the full sweep is 0.25,0.5,0.75,0.9,1.1)")
     ap.add_argument("--serve-requests", type=int, default=8,
                     help="requests per rate (cut from the 2,000 of the full stream to keep the run "
-                         "within minutes: the mean request has about 25M dofs)")
+                         "within minutes: the mean request has about 17M dofs)")
     ap.add_argument("--no-64m", action="store_true", help="skip the 64M-dof apply sweep")
     ap.add_argument("--no-mixed", action="store_true", help="skip the ~30M-dof mixed-precision solves")
     ap.add_argument("--no-curve", action="store_true", help="skip the CG launch-form size curve")
