@@ -114,3 +114,18 @@ def test_server_needs_gpu_and_footprint_is_consistent():
     qd = 8 ** 3 * 6 ** 3 * 6 * 8
     assert qd < f1 < 2 * qd and 7.5 < f2 / f1 < 8.5
     assert fir - f1 >= 8 ** 3 * 6 ** 3 * 6 * 4       # FP32 copy of the quadrature data
+
+
+def test_sizes_beyond_32_bit_indexing_are_refused():
+    """The kernels index nodes and E-vector words in 32 bits: a space whose
+    E-vector or lattice would pass 2^31 - 1 is refused at creation (nothing is
+    allocated), the largest that fits is accepted."""
+    ctx = pafem.Context(-1)
+    n = 162  # p = 8: 162^3 * 9^3 = 3.1e9 E-vector words, 1297^3 = 2.18e9 nodes
+    mesh = pafem.Mesh(ctx, n, n, n, inputs.perturbed_vertices(n, n, n, seed=None))
+    with pytest.raises(pafem.PafemError) as ei:
+        pafem.Space(mesh, 8)
+    assert ei.value.name == "INVALID_ARG" and "int32" in str(ei.value)
+    # p = 6 on the same mesh: 162^3 * 343 = 1.46e9 words and 973^3 = 9.2e8 nodes fit
+    sp = pafem.Space(mesh, 6)
+    assert sp.ndofs == 973 ** 3
