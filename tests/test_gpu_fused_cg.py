@@ -146,3 +146,19 @@ def test_launch_forms_rejected_where_unavailable(pf, ctx):
         op.solve(op.rhs(), launch=pf.LAUNCH_PERSISTENT)
     with pytest.raises(pf.PafemError):
         op.solve(op.rhs(), launch=7)
+
+
+@pytest.mark.parametrize("n,p", [(1, 3), (2, 2), (2, 5)])
+def test_persistent_grid_smaller_than_the_xcd_count(pf, ctx, n, p):
+    """Grids of 1..7 workgroups: every workgroup is its own barrier group and
+    walks the items with a plain stride; the solve matches the oracle."""
+    v = inputs.perturbed_vertices(n, n, n, seed=inputs.mesh_seed(p, n))
+    op = pf.Operator(pf.Space(pf.Mesh(ctx, n, n, n, v), p), pf.DIFFUSION)
+    op.assemble()
+    b = op.rhs()
+    xk, sk = op.solve(b, rtol=1e-10, check_every=4)
+    xp, sp_ = op.solve(b, rtol=1e-10, check_every=4, launch=pf.LAUNCH_PERSISTENT)
+    assert sp_["true_rel_res"] <= 1e-10 and abs(sp_["iterations"] - sk["iterations"]) <= 1
+    ref = fem.solve_poisson(v, n, n, n, p, f=inputs.f_manufactured, rtol=1e-12)
+    xr = ref["x"]
+    assert np.linalg.norm(xp.cpu().numpy() - xr) <= 1e-8 * max(np.linalg.norm(xr), 1e-300)

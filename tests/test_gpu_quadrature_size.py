@@ -169,3 +169,13 @@ def test_unsupported_combinations_are_refused(pf, ctx):
     with pytest.raises(pf.PafemError):
         op.solve(op.rhs(), launch=pf.LAUNCH_PERSISTENT)
     assert op.qdata_bytes(pf.FP64) == 8 * 6 ** 3 * 6 * 8
+
+
+def test_allocation_free_apply_with_other_rule(pf, ctx):
+    mesh = (3, 2, 2)
+    _, op = _op(pf, ctx, "diffusion", mesh, 4, 8, seed=17, prec=pf.FP64)
+    x = torch.from_numpy(inputs.random_vector(op.space.ndofs, 3)).cuda()
+    y0 = op.apply(x, constrained=True)
+    y1 = torch.empty_like(x)
+    op.apply_noalloc(x, y1, constrained=True)
+    assert torch.equal(y0, y1)
