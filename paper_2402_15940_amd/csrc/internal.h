@@ -394,8 +394,10 @@ hipError_t launch_sum_final(const double* partials, int nb, int ncols, double* o
 template <typename T>
 hipError_t launch_cg_init(const T* r, const T* dinv, T* p, int64_t n, double* partials, int nb,
                           hipStream_t s);
+// bb_dev, when given, is read on the device in place of bb (b . b stays there).
 hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
-                                int maxit, CgState* st, hipStream_t s, double delta2 = 0.0);
+                                int maxit, CgState* st, hipStream_t s, double delta2 = 0.0,
+                                const double* bb_dev = nullptr);
 // One CG step fused into the ordered E^T sum of the x-interleaved E-vector
 // yX of A p: x += alpha p, r -= alpha A p, and fixed-partition partials of
 // (r . dinv r, r . r) (*nparts pairs, at most kMaxCgParts).  A p is not stored.
@@ -479,7 +481,9 @@ hipError_t launch_batch_iterations(const BatchEntry<T>* ents, const BatchHeader*
 
 // Mixed-precision helpers.
 hipError_t launch_residual(const double* b, const double* Ax, double* r, int64_t n,
-                           hipStream_t s);
+                           hipStream_t s, const int* skip = nullptr);
+// *flag = 1 while the CG of st runs, 0 once it is done.
+hipError_t launch_running_flag(const CgState* st, int* flag, hipStream_t s);
 hipError_t launch_scale_to_f32(const double* r, const double* norm2, float* r32, int64_t n,
                                hipStream_t s);
 hipError_t launch_axpy_from_f32(double* x, const double* norm2, const float* d32, int64_t n,

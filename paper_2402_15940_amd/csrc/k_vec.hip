@@ -240,11 +240,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(const T* __restrict__ r,
   }
 }
 
-__global__ void k_cg_init_final(const double* __restrict__ partials, int nb, double bb,
-                                double rtol, int maxit, double delta2, CgState* st) {
+__global__ void k_cg_init_final(const double* __restrict__ partials, int nb, double bb_host,
+                                const double* __restrict__ bb_dev, double rtol, int maxit,
+                                double delta2, CgState* st) {
   double r[4];
   final_sums(partials, nb, 2, r);
   if (threadIdx.x == 0) {
+    const double bb = bb_dev != nullptr ? *bb_dev : bb_host;
     st->rz = r[0];
     st->rr = r[1];
     st->bb = bb;
@@ -374,7 +376,9 @@ __global__ void k_replace_final(const double* __restrict__ partials, int nb, CgS
 
 __global__ __launch_bounds__(kThreads) void k_residual(const double* __restrict__ b,
                                                        const double* __restrict__ Ax,
-                                                       double* __restrict__ r, int64_t n) {
+                                                       double* __restrict__ r, int64_t n,
+                                                       const int* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads)
     r[i] = b[i] - Ax[i];
@@ -554,9 +558,10 @@ template hipError_t launch_cg_init<float>(const float*, const float*, float*, in
                                           int, hipStream_t);
 
 hipError_t launch_cg_init_final(const double* partials, int nb, double bb, double rtol,
-                                int maxit, CgState* st, hipStream_t s, double delta2) {
-  hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kThreads), 0, s, partials, nb, bb, rtol,
-                     maxit, delta2, st);
+                                int maxit, CgState* st, hipStream_t s, double delta2,
+                                const double* bb_dev) {
+  hipLaunchKernelGGL(k_cg_init_final, dim3(1), dim3(kThreads), 0, s, partials, nb, bb, bb_dev,
+                     rtol, maxit, delta2, st);
   return hipGetLastError();
 }
 
@@ -609,8 +614,19 @@ template hipError_t launch_cg_pupdate<float>(float*, const float*, const float*,
                                              const CgState*, hipStream_t);
 
 hipError_t launch_residual(const double* b, const double* Ax, double* r, int64_t n,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(kThreads), 0, s, b, Ax, r, n);
+                           hipStream_t s, const int* skip) {
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(kThreads), 0, s, b, Ax, r, n, skip);
+  return hipGetLastError();
+}
+
+// *flag = 1 while the CG of st is still running, 0 once it is done (the skip
+// flag of work that only a finished CG needs)
+__global__ void k_running_flag(const CgState* __restrict__ st, int* __restrict__ flag) {
+  *flag = st->done ? 0 : 1;
+}
+
+hipError_t launch_running_flag(const CgState* st, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_running_flag, dim3(1), dim3(1), 0, s, st, flag);
   return hipGetLastError();
 }
 

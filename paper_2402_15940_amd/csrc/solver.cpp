@@ -26,6 +26,7 @@ struct CgResult {
   int iterations = 0;
   double rr = 0.0, bb = 0.0;
   bool converged = false;
+  double true_rr = -1.0;  // ||b - A x||^2 in FP64 when the check was enqueued (else -1)
 };
 
 // Reduction partials: pairs for the vector kernels (reduce_blocks) and for the
@@ -147,26 +148,45 @@ constexpr long long kSpinLimit = 1LL << 24;
 // below this fraction of its value before it, or the inner solves switch to FP64.
 constexpr double kIrStagnation = 0.9;
 
+// The FP64 residual check of a finished CG, enqueued behind a batch of
+// iterations: once the CG is done, r = b - A x and its squared norm go to
+// true_rr (the kernels skip while it still runs), so the host reads the state
+// and the check with one synchronization.
+int enqueue_true_residual(Op* op, const double* b, const double* x, double* r, double* Ax,
+                          double* part, int* running, double* true_rr, const CgState* st,
+                          hipStream_t s) {
+  const int64_t n = op->space->ndofs;
+  const int nb = reduce_blocks(n);
+  PAFEM_TRY_HIP(launch_running_flag(st, running, s));
+  PAFEM_TRY(apply_impl<double>(op, x, Ax, PAFEM_APPLY_CONSTRAINED, running, s));
+  PAFEM_TRY_HIP(launch_residual(b, Ax, r, n, s, running));
+  PAFEM_TRY_HIP(launch_dot_partial<double>(r, r, n, part, nb, running, s));
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, true_rr, s));
+  return PAFEM_OK;
+}
+
+// true_b: when given (T = double), the FP64 residual check of the finished CG
+// is enqueued behind every batch of iterations (res.true_rr).
 template <typename T>
 int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T* dinv,
             double rtol, int maxit, int check_every, hipStream_t s, CgResult& res,
-            int qprec = 0, int launch = PAFEM_LAUNCH_KERNELS) {
+            int qprec = 0, int launch = PAFEM_LAUNCH_KERNELS, const double* true_b = nullptr) {
   Space* sp = op->space;
   const int64_t n = sp->ndofs;
   const int nb = reduce_blocks(n);
   PAFEM_TRY(ensure_partials(op, n));
   PAFEM_TRY(op->d_state.ensure(sizeof(CgState)));
   double* part = op->d_part.as<double>();
+  // scalar slots after the partials: 0 b.b, 2 the IR outer ||r||^2, 4 the
+  // residual check, 6 the running flag
   double* bbdev = part + 2 * partial_pairs(n);
+  double* true_rr_dev = bbdev + 4;
+  int* running = reinterpret_cast<int*>(bbdev + 6);
   CgState* st = op->d_state.as<CgState>();
 
-  // b.b for the stopping test
+  // b.b for the stopping test, kept on the device
   PAFEM_TRY_HIP(launch_dot_partial<T>(rhs, rhs, n, part, nb, nullptr, s));
   PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, bbdev, s));
-  double bb = 0.0;
-  PAFEM_TRY_HIP(hipMemcpyAsync(&bb, bbdev, sizeof(double), hipMemcpyDeviceToHost, s));
-  PAFEM_TRY_HIP(hipStreamSynchronize(s));
-  res.bb = bb;
 
   // r = rhs - A x
   if (x0_zero) {
@@ -183,9 +203,22 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
     }
   }
   PAFEM_TRY_HIP(launch_cg_init<T>(r, dinv, p, n, part, nb, s));
-  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, bb, rtol, maxit, st, s));
+  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, 0.0, rtol, maxit, st, s, 0.0, bbdev));
 
   CgState hs{};
+  double hrr = -1.0;
+  // behind each batch: the residual check (plain FP64 solves), then one read
+  auto check = [&]() -> int {
+    if constexpr (std::is_same<T, double>::value) {
+      if (true_b != nullptr) {
+        PAFEM_TRY(enqueue_true_residual(op, true_b, x, r, Ap, part, running, true_rr_dev, st, s));
+        PAFEM_TRY_HIP(
+            hipMemcpyAsync(&hrr, true_rr_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+      }
+    }
+    PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    return PAFEM_OK;
+  };
   if (launch == PAFEM_LAUNCH_PERSISTENT) {
     if constexpr (std::is_same<T, double>::value) {
       ApplyArgs<double> a{};
@@ -207,7 +240,7 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
                                             st, bar, err, kSpinLimit, check_every,
                                             kMaxPersistentBlocks, &grid, s));
         int herr = 0;
-        PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        PAFEM_TRY(check());
         PAFEM_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
         PAFEM_TRY_HIP(hipStreamSynchronize(s));
         if (herr) {
@@ -225,21 +258,23 @@ int run_pcg(Op* op, const T* rhs, T* x, bool x0_zero, T* r, T* p, T* Ap, const T
     PAFEM_TRY((cg_graph<T>(op, x, r, p, Ap, dinv, part, st, check_every, qprec, &g)));
     for (;;) {
       PAFEM_TRY_HIP(hipGraphLaunch(g, s));
-      PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      PAFEM_TRY(check());
       PAFEM_TRY_HIP(hipStreamSynchronize(s));
       if (hs.done) break;
     }
   } else {
     for (;;) {
       PAFEM_TRY((enqueue_iterations<T>(op, x, r, p, Ap, dinv, part, st, check_every, s, qprec)));
-      PAFEM_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+      PAFEM_TRY(check());
       PAFEM_TRY_HIP(hipStreamSynchronize(s));
       if (hs.done) break;
     }
   }
   res.iterations = hs.iter;
   res.rr = hs.rr;
+  res.bb = hs.bb;
   res.converged = hs.rr <= hs.rr_stop;
+  res.true_rr = hrr;
   return PAFEM_OK;
 }
 
@@ -263,17 +298,13 @@ int run_mixed(Op* op, const double* b, double* x, double* r64, double* Ax, float
   CgState* st = op->d_state.as<CgState>();
 
   PAFEM_TRY_HIP(launch_dot_partial<double>(b, b, n, part, nb, nullptr, s));
-  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, bbdev, s));
-  double bb = 0.0;
-  PAFEM_TRY_HIP(hipMemcpyAsync(&bb, bbdev, sizeof(double), hipMemcpyDeviceToHost, s));
-  PAFEM_TRY_HIP(hipStreamSynchronize(s));
-  res.bb = bb;
+  PAFEM_TRY_HIP(launch_sum_final(part, nb, 1, bbdev, s));  // b.b stays on the device
 
   // r64 = b - A x, rs = (float) r64, p = dinv .* rs
   PAFEM_TRY(apply_impl<double>(op, x, Ax, PAFEM_APPLY_CONSTRAINED, nullptr, s));
   PAFEM_TRY_HIP(launch_residual(b, Ax, r64, n, s));
   PAFEM_TRY_HIP(launch_replace_residual(r64, dinv, rs, n, part, nb, nullptr, s));
-  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, bb, rtol, maxit, st, s, delta * delta));
+  PAFEM_TRY_HIP(launch_cg_init_final(part, nb, 0.0, rtol, maxit, st, s, delta * delta, bbdev));
   PAFEM_TRY_HIP(launch_fill<float>(p, n, 0.0f, nullptr, s));
   PAFEM_TRY_HIP(launch_cg_pupdate<float>(p, rs, dinv, n, st, s));  // beta = 0 here: p = z
 
@@ -309,6 +340,7 @@ int run_mixed(Op* op, const double* b, double* x, double* r64, double* Ax, float
   }
   res.iterations = hs.iter;
   res.rr = hs.rr;
+  res.bb = hs.bb;
   res.converged = hs.rr <= hs.rr_stop;
   return PAFEM_OK;
 }
@@ -495,11 +527,17 @@ extern "C" int pafem_solve_cg(pafem_op* op_, const double* b, double* x,
     }
     for (;;) {
       CgResult res;
+      // with more than one iteration per host check, the FP64 residual check
+      // rides behind each batch (no separate round trip)
       PAFEM_TRY(run_pcg<double>(op, b, xs, false, r, p, Ap, op->d_dinv64.as<double>(), o->rtol,
-                                o->maxit - total, o->check_every, s, res, 0, o->launch));
+                                o->maxit - total, o->check_every, s, res, 0, o->launch,
+                                o->check_every > 1 ? b : nullptr));
       total += res.iterations;
       rel = res.bb > 0 ? std::sqrt(res.rr / res.bb) : 0.0;
-      PAFEM_TRY(true_residual(op, b, xs, Ap, r, res.bb, s, true_rel));
+      if (res.true_rr >= 0.0)
+        true_rel = res.bb > 0.0 ? std::sqrt(res.true_rr / res.bb) : std::sqrt(res.true_rr);
+      else
+        PAFEM_TRY(true_residual(op, b, xs, Ap, r, res.bb, s, true_rel));
       if (true_rel <= o->rtol) {
         ok = true;
         break;
