@@ -388,6 +388,60 @@ def test_full_size_sampled_rows(pf, ctx, p, target):
         torch.cuda.synchronize()
 
 
+def _elements_of_node(i, N, p):
+    """(element, local index) pairs holding lattice node i of an N^3 mesh of order p."""
+    L = N * p + 1
+    I, J, K = i % L, (i // L) % L, i // (L * L)
+
+    def cands(c):
+        out = []
+        for e in (c // p - 1, c // p):
+            if 0 <= e < N and 0 <= c - e * p <= p:
+                out.append((e, c - e * p))
+        return out
+
+    res = []
+    for ez, lz in cands(K):
+        for ey, ly in cands(J):
+            for ex, lx in cands(I):
+                res.append((ex + N * (ey + N * ez), lx + (p + 1) * (ly + (p + 1) * lz)))
+    return res
+
+
+@pytest.mark.parametrize("p,N", [(4, 100), (7, 64)])
+def test_largest_sizes_sampled_rows(pf, ctx, p, N):
+    """The largest stated sizes: p=4 on 64.5M dofs (the apply sweep's top size)
+    and p=7 on the 64^3 mesh of 90.5M dofs (the large solve), in the launch
+    configuration the benchmark times (deterministic E^T on the lattice
+    numbering): sampled rows against the oracle's element matrices."""
+    seed = inputs.mesh_seed(p, N)
+    v = inputs.perturbed_vertices(N, N, N, seed=seed)
+    sp = pf.Space(pf.Mesh(ctx, N, N, N, v), p)
+    print(f"largest-size apply p={p} N={N} ndofs={sp.ndofs}", flush=True)
+    x = inputs.random_vector(sp.ndofs, inputs.vector_seed(p, N))
+    E = fem.element_restriction(N, N, N, p)
+    ref = fem.reference_matrices(p, p + 2)
+    L = N * p + 1
+    rng = np.random.default_rng(100 + p)
+    dofs = np.unique(np.concatenate([[0, L - 1, L * L // 2 + p, (L ** 3) // 2, sp.ndofs - 1],
+                                     rng.integers(0, sp.ndofs, 10)]))
+    op = pf.Operator(sp, pf.DIFFUSION)
+    op.assemble()
+    y = op.apply(torch.from_numpy(x).cuda())[torch.from_numpy(dofs).cuda()].cpu().numpy()
+    yo = []
+    for i in dofs:
+        acc = 0.0
+        for e, l in _elements_of_node(int(i), N, p):
+            assert E[e, l] == i
+            Ae = fem.element_diffusion(_corners(v, N, N, N, e), p, p + 2, ref=ref)
+            acc += Ae[l] @ x[E[e]]
+        yo.append(acc)
+    yo = np.array(yo)
+    np.testing.assert_allclose(y, yo, rtol=1e-12, atol=1e-12 * np.abs(yo).max())
+    del op
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("p,target", [(1, 8e6), (3, 8e6), (6, 8e6), (7, 8e6)])
 def test_full_size_invariants(pf, ctx, p, target):
     N = inputs.mesh_n_for_dofs(p, target)
