@@ -215,13 +215,19 @@ def serve_benchmark(pf, ctx, rate, n_req, n_range, p_range, budget, max_slots, i
     srv = pf.Server(ctx, budget, max_slots=max_slots, iters_per_round=iters)
     tickets = []
     t0 = time.perf_counter()
-    for r, v in zip(stream, verts):
+    t_log = t0
+    for i, (r, v) in enumerate(zip(stream, verts)):
         dt = r["t_arrive"] - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
         n = r["N"]
         tickets.append(srv.submit(n, n, n, r["p"], v, mode=pf.SOLVE_MIXED_FP32, rtol=1e-10,
                                   inner_rtol=0.1, coef_kind=pf.COEF_CONST, coef_value=1.0))
+        if time.perf_counter() - t_log >= 30.0:
+            t_log = time.perf_counter()
+            done = sum(srv.poll(t)["status"] == pf.REQ_DONE for t in tickets)
+            log(f"serving at {rate:.3g}/s: {i + 1} of {n_req} submitted, {done} done, "
+                f"{t_log - t0:.0f} s")
     srv.drain()
     res = [srv.poll(t) for t in tickets]
     st = srv.stats()
@@ -461,9 +467,8 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the p=7 64^3 (90M dofs) single solve")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-fracs", type=str, default="0.25,0.5,0.9,1.1",
-                    help="arrival rates of the serving stream as fractions of its measured capacity "
-                         "(the full sweep is 0.25,0.5,0.75,0.9,1.1)")
+    ap.add_argument("--serve-fracs", type=str, default="0.25,0.5,0.75,0.9,1.1",
+                    help="arrival rates of the serving stream as fractions of its measured capacity")
     ap.add_argument("--serve-requests", type=int, default=8,
                     help="requests per rate (cut from the 2,000 of the full stream to keep the run "
                          "within minutes: the mean request has about 17M dofs)")
