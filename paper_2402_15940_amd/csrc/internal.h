@@ -370,9 +370,23 @@ hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int
                                  int accumulate, const T* x, T* y, const int* skip,
                                  hipStream_t s);
 // The same sum from the x-interleaved layout.
+// nt: non-temporal E-vector loads (see evec_nt_loads).
 template <typename T>
 hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int constrained,
-                               int accumulate, const T* x, T* y, const int* skip, hipStream_t s);
+                               int accumulate, const T* x, T* y, const int* skip, hipStream_t s,
+                               bool nt = false);
+
+// E-vector loads of the ordered sums, by p, for FP64 diffusion operators:
+// 1 = non-temporal, 0 = ordinary.  Measured on MI355X: non-temporal loads
+// shorten the p=6 FP64 diffusion apply by 5% and lengthen every other order,
+// the FP32 applies and the mass applies by 1-10%.
+#ifndef PAFEM_NT_EVEC_DIFF64_BY_P
+#define PAFEM_NT_EVEC_DIFF64_BY_P 0, 0, 0, 0, 0, 0, 1, 0, 0
+#endif
+inline bool evec_nt_loads(int kind, int p, bool f64) {
+  constexpr int by_p[] = {PAFEM_NT_EVEC_DIFF64_BY_P};
+  return kind == PAFEM_DIFFUSION && f64 && p >= 1 && p <= 8 && by_p[p] != 0;
+}
 
 // Essential-dof fix-up: y[ess[i]] (+)= x ? x[ess[i]] : value.
 template <typename T>
@@ -405,7 +419,7 @@ constexpr int kMaxCgParts = 4096;
 template <typename T, typename TX>
 hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int p, const T* pvec,
                                   TX* x, T* r, const T* dinv, double* partials, int* nparts,
-                                  const CgState* st, hipStream_t s);
+                                  const CgState* st, hipStream_t s, bool nt = false);
 // alpha from nb partials of p . A p (one 1024-thread workgroup).
 hipError_t launch_cg_alpha_wide(const double* partials, int nb, CgState* st, hipStream_t s);
 // Element pass of A p for CG (deterministic E^T, lattice numbering): writes the

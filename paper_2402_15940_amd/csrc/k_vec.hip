@@ -68,7 +68,7 @@ using vec::xrows_geom;
 using vec::xrows_load;
 using vec::xrows_sum;
 
-template <typename T, int P>
+template <typename T, int P, bool NT>
 __global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__ yX, XRowsGeom g,
                                                            int constrained, int accumulate,
                                                            const T* __restrict__ x,
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int64_t iq = base + q * kThreads;
-    xrows_load<T, P>(yX, g, (int)(iq < g.n ? iq : g.n - 1), L[q]);
+    xrows_load<T, P, NT>(yX, g, (int)(iq < g.n ? iq : g.n - 1), L[q]);
   }
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__
 // and each workgroup's partials of (r . z, r . r).  A p never goes through
 // memory.  A capped grid strides over the chunks of nodes; TX is the type of
 // the solution (FP64 for mixed CG).
-template <typename T, typename TX, int P>
+template <typename T, typename TX, int P, bool NT>
 __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
     const T* __restrict__ yX, XRowsGeom g, const T* __restrict__ p, TX* __restrict__ x,
     T* __restrict__ r, const T* __restrict__ dinv, double* __restrict__ partials,
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows_cg(
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int64_t iq = base + q * kThreads;
-      xrows_load<T, P>(yX, g, (int)(iq < g.n ? iq : g.n - 1), L[q]);
+      xrows_load<T, P, NT>(yX, g, (int)(iq < g.n ? iq : g.n - 1), L[q]);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -471,37 +471,44 @@ hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int
 }
 template <typename T, int P>
 hipError_t gather_xrows_p(const T* yX, int nx, int ny, int nz, int constrained, int accumulate,
-                          const T* x, T* y, const int* skip, hipStream_t s) {
+                          const T* x, T* y, const int* skip, hipStream_t s, bool nt) {
   const int64_t nodes = ((int64_t)nx * P + 1) * ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
   const int64_t per = (int64_t)kThreads * kXRowsNodes;
-  hipLaunchKernelGGL((k_gather_xrows<T, P>), dim3((unsigned)((nodes + per - 1) / per)),
-                     dim3(kThreads), 0, s, yX, xrows_geom(nx, ny, nz, P), constrained, accumulate,
-                     x, y, skip);
+  const dim3 grid((unsigned)((nodes + per - 1) / per));
+  if (nt)
+    hipLaunchKernelGGL((k_gather_xrows<T, P, true>), grid, dim3(kThreads), 0, s, yX,
+                       xrows_geom(nx, ny, nz, P), constrained, accumulate, x, y, skip);
+  else
+    hipLaunchKernelGGL((k_gather_xrows<T, P, false>), grid, dim3(kThreads), 0, s, yX,
+                       xrows_geom(nx, ny, nz, P), constrained, accumulate, x, y, skip);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int constrained,
-                               int accumulate, const T* x, T* y, const int* skip, hipStream_t s) {
+                               int accumulate, const T* x, T* y, const int* skip, hipStream_t s,
+                               bool nt) {
   const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
   if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
   if (Lx * Ly * Lz > 0x7fffffff) return hipErrorInvalidValue;
   switch (p) {
-    case 1: return gather_xrows_p<T, 1>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 2: return gather_xrows_p<T, 2>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 3: return gather_xrows_p<T, 3>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 4: return gather_xrows_p<T, 4>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 5: return gather_xrows_p<T, 5>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 6: return gather_xrows_p<T, 6>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 7: return gather_xrows_p<T, 7>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
-    case 8: return gather_xrows_p<T, 8>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s);
+    case 1: return gather_xrows_p<T, 1>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 2: return gather_xrows_p<T, 2>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 3: return gather_xrows_p<T, 3>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 4: return gather_xrows_p<T, 4>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 5: return gather_xrows_p<T, 5>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 6: return gather_xrows_p<T, 6>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 7: return gather_xrows_p<T, 7>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 8: return gather_xrows_p<T, 8>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
     default: return hipErrorInvalidValue;
   }
 }
 template hipError_t launch_gather_xrows<double>(const double*, int, int, int, int, int, int,
-                                                const double*, double*, const int*, hipStream_t);
+                                                const double*, double*, const int*, hipStream_t,
+                                                bool);
 template hipError_t launch_gather_xrows<float>(const float*, int, int, int, int, int, int,
-                                               const float*, float*, const int*, hipStream_t);
+                                               const float*, float*, const int*, hipStream_t,
+                                               bool);
 template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int,
                                                   const double*, double*, const int*, hipStream_t);
 template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int,
@@ -651,21 +658,25 @@ hipError_t launch_recip(const double* d, double* dinv64, float* dinv32, int64_t 
 template <typename T, typename TX, int P>
 hipError_t gather_xrows_cg_p(const T* yX, int nx, int ny, int nz, const T* p, TX* x, T* r,
                              const T* dinv, double* partials, int* nparts, const CgState* st,
-                             hipStream_t s) {
+                             hipStream_t s, bool nt) {
   const int64_t nodes = ((int64_t)nx * P + 1) * ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
   const int64_t per = (int64_t)kThreads * kXRowsNodes;
   int64_t nblk = (nodes + per - 1) / per;
   if (nblk > kMaxCgParts) nblk = kMaxCgParts;  // the workgroups stride over the rest
   *nparts = (int)nblk;
-  hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P>), dim3((unsigned)nblk), dim3(kThreads), 0, s,
-                     yX, xrows_geom(nx, ny, nz, P), p, x, r, dinv, partials, st);
+  if (nt)
+    hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P, true>), dim3((unsigned)nblk), dim3(kThreads), 0,
+                       s, yX, xrows_geom(nx, ny, nz, P), p, x, r, dinv, partials, st);
+  else
+    hipLaunchKernelGGL((k_gather_xrows_cg<T, TX, P, false>), dim3((unsigned)nblk), dim3(kThreads),
+                       0, s, yX, xrows_geom(nx, ny, nz, P), p, x, r, dinv, partials, st);
   return hipGetLastError();
 }
 
 template <typename T, typename TX>
 hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int pdeg, const T* p,
                                   TX* x, T* r, const T* dinv, double* partials, int* nparts,
-                                  const CgState* st, hipStream_t s) {
+                                  const CgState* st, hipStream_t s, bool nt) {
   if (nx <= 0 || ny <= 0 || nz <= 0 || pdeg < 1) return hipErrorInvalidValue;
   const int64_t nodes = ((int64_t)nx * pdeg + 1) * ((int64_t)ny * pdeg + 1) *
                         ((int64_t)nz * pdeg + 1);
@@ -673,7 +684,8 @@ hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int pdeg,
   switch (pdeg) {
 #define PAFEM_CASE(PP) \
   case PP:             \
-    return gather_xrows_cg_p<T, TX, PP>(yX, nx, ny, nz, p, x, r, dinv, partials, nparts, st, s);
+    return gather_xrows_cg_p<T, TX, PP>(yX, nx, ny, nz, p, x, r, dinv, partials, nparts, st, s, \
+                                        nt);
     PAFEM_CASE(1) PAFEM_CASE(2) PAFEM_CASE(3) PAFEM_CASE(4)
     PAFEM_CASE(5) PAFEM_CASE(6) PAFEM_CASE(7) PAFEM_CASE(8)
 #undef PAFEM_CASE
@@ -683,15 +695,15 @@ hipError_t launch_gather_xrows_cg(const T* yX, int nx, int ny, int nz, int pdeg,
 template hipError_t launch_gather_xrows_cg<double, double>(const double*, int, int, int, int,
                                                            const double*, double*, double*,
                                                            const double*, double*, int*,
-                                                           const CgState*, hipStream_t);
+                                                           const CgState*, hipStream_t, bool);
 template hipError_t launch_gather_xrows_cg<float, float>(const float*, int, int, int, int,
                                                          const float*, float*, float*,
                                                          const float*, double*, int*,
-                                                         const CgState*, hipStream_t);
+                                                         const CgState*, hipStream_t, bool);
 template hipError_t launch_gather_xrows_cg<float, double>(const float*, int, int, int, int,
                                                           const float*, double*, float*,
                                                           const float*, double*, int*,
-                                                          const CgState*, hipStream_t);
+                                                          const CgState*, hipStream_t, bool);
 
 hipError_t launch_cg_alpha_wide(const double* partials, int nb, CgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_alpha_wide, dim3(1), dim3(kWideThreads), 0, s, partials, nb, st);

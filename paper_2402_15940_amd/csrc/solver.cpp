@@ -58,9 +58,11 @@ int cg_step_fused(Op* op, TX* x, T* r, const T* p, const T* dinv, double* part, 
   int ne_parts = 0, g_parts = 0;
   PAFEM_TRY(apply_elements_dot<T>(op, p, &st->done, s, qprec, &ne_parts));
   PAFEM_TRY_HIP(launch_cg_alpha_wide(op->d_gpart.as<double>(), ne_parts, st, s));
+  const bool nt = op->level == PAFEM_ASSEMBLY_PARTIAL &&
+                  evec_nt_loads(op->kind, sp->p, sizeof(T) == sizeof(double));
   PAFEM_TRY_HIP((launch_gather_xrows_cg<T, TX>(op->d_evec.as<T>(), sp->mesh->nx, sp->mesh->ny,
                                                sp->mesh->nz, sp->p, p, x, r, dinv, part,
-                                               &g_parts, st, s)));
+                                               &g_parts, st, s, nt)));
   PAFEM_TRY_HIP(launch_cg_beta(part, g_parts, st, s));
   return PAFEM_OK;
 }

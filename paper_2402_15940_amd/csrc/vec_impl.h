@@ -200,7 +200,17 @@ struct XRowsLoads {
   bool hy, hz, xf, ess;
 };
 
-template <typename T, int P>
+// One E-vector word: an ordinary or a non-temporal load (NT), as measured
+// per operator and order.
+template <bool NT, typename T>
+__device__ __forceinline__ T evec_word(const T* __restrict__ p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <typename T, int P, bool NT = false>
 __device__ __forceinline__ void xrows_load(const T* __restrict__ yX, const XRowsGeom& g, int i,
                                            XRowsLoads<T>& L) {
   constexpr int N = P + 1, W = xrows_width(N);
@@ -223,18 +233,18 @@ __device__ __forceinline__ void xrows_load(const T* __restrict__ yX, const XRows
   const int o = (((ez * g.ny + ey) * N + lz) * N + ly) * rowlen + ex * W + a;
   const int dy = (N * N - P) * rowlen, dz = N * (g.ny * N - P) * rowlen;
   const int left = L.xf ? P - W : 0;
-  L.v[0] = yX[o];
-  L.w[0] = yX[o + left];
+  L.v[0] = evec_word<NT>(yX + o);
+  L.w[0] = evec_word<NT>(yX + o + left);
   if (L.hy) {
-    L.v[1] = yX[o - dy];
-    L.w[1] = yX[o - dy + left];
+    L.v[1] = evec_word<NT>(yX + o - dy);
+    L.w[1] = evec_word<NT>(yX + o - dy + left);
   }
   if (L.hz) {
-    L.v[2] = yX[o - dz];
-    L.w[2] = yX[o - dz + left];
+    L.v[2] = evec_word<NT>(yX + o - dz);
+    L.w[2] = evec_word<NT>(yX + o - dz + left);
     if (L.hy) {
-      L.v[3] = yX[o - dz - dy];
-      L.w[3] = yX[o - dz - dy + left];
+      L.v[3] = evec_word<NT>(yX + o - dz - dy);
+      L.w[3] = evec_word<NT>(yX + o - dz - dy + left);
     }
   }
 }
