@@ -211,10 +211,12 @@ int apply_impl(Op* op, const T* x, T* y, int flags, const int* skip, hipStream_t
     // lattice numbering, nothing allocated (the maps are not needed)
     ApplyArgs<T> a = make_args<T>(op, x, y, static_cast<T*>(work), flags, skip, qprec);
     PAFEM_TRY_HIP(launch_apply<T>(op->kind, sp->p, op->q, kScatterXRows, PAFEM_INDEX_LATTICE, a, s));
-    const bool nt = op->level == PAFEM_ASSEMBLY_PARTIAL && op->q == sp->p + 2 &&
-                    evec_nt_loads(op->kind, sp->p, sizeof(T) == sizeof(double));
+    const bool tuned = op->level == PAFEM_ASSEMBLY_PARTIAL && op->q == sp->p + 2;
+    const bool f64 = sizeof(T) == sizeof(double);
     PAFEM_TRY_HIP(launch_gather_xrows<T>(a.yE, a.nx, a.ny, a.nz, sp->p, a.constrained,
-                                         a.accumulate, x, y, skip, s, nt));
+                                         a.accumulate, x, y, skip, s,
+                                         tuned && evec_nt_loads(op->kind, sp->p, f64),
+                                         tuned && y_nt_stores(op->kind, sp->p, f64)));
     return PAFEM_OK;
   }
   const int im = op->index_mode;

@@ -370,11 +370,12 @@ hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int
                                  int accumulate, const T* x, T* y, const int* skip,
                                  hipStream_t s);
 // The same sum from the x-interleaved layout.
-// nt: non-temporal E-vector loads (see evec_nt_loads).
+// nt: non-temporal E-vector loads (see evec_nt_loads); nt_y: non-temporal
+// stores of y (see y_nt_stores).
 template <typename T>
 hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int constrained,
                                int accumulate, const T* x, T* y, const int* skip, hipStream_t s,
-                               bool nt = false);
+                               bool nt = false, bool nt_y = false);
 
 // E-vector loads of the ordered sums, by p, for FP64 diffusion operators:
 // 1 = non-temporal, 0 = ordinary.  Measured on MI355X: non-temporal loads
@@ -386,6 +387,24 @@ hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int c
 inline bool evec_nt_loads(int kind, int p, bool f64) {
   constexpr int by_p[] = {PAFEM_NT_EVEC_DIFF64_BY_P};
   return kind == PAFEM_DIFFUSION && f64 && p >= 1 && p <= 8 && by_p[p] != 0;
+}
+// Stores of y in the ordered sum of an apply, by p, for the FP64 diffusion
+// and mass operators: 1 = non-temporal, 0 = ordinary; FP32 applies always
+// store non-temporally.  Measured on MI355X: non-temporal stores shorten the
+// applies by 1-4% except FP64 diffusion at p = 6, 8 and FP64 mass at p >= 6,
+// where they cost up to 1%.
+#ifndef PAFEM_NT_Y_DIFF64_BY_P
+#define PAFEM_NT_Y_DIFF64_BY_P 0, 1, 1, 1, 1, 1, 0, 1, 0
+#endif
+#ifndef PAFEM_NT_Y_MASS64_BY_P
+#define PAFEM_NT_Y_MASS64_BY_P 0, 1, 1, 1, 1, 1, 0, 0, 0
+#endif
+inline bool y_nt_stores(int kind, int p, bool f64) {
+  constexpr int diff[] = {PAFEM_NT_Y_DIFF64_BY_P};
+  constexpr int mass[] = {PAFEM_NT_Y_MASS64_BY_P};
+  if (p < 1 || p > 8) return false;
+  if (!f64) return true;
+  return (kind == PAFEM_DIFFUSION ? diff[p] : mass[p]) != 0;
 }
 
 // Essential-dof fix-up: y[ess[i]] (+)= x ? x[ess[i]] : value.

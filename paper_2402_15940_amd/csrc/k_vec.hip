@@ -68,7 +68,7 @@ using vec::xrows_geom;
 using vec::xrows_load;
 using vec::xrows_sum;
 
-template <typename T, int P, bool NT>
+template <typename T, int P, bool NT, bool NTY>
 __global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__ yX, XRowsGeom g,
                                                            int constrained, int accumulate,
                                                            const T* __restrict__ x,
@@ -91,7 +91,11 @@ __global__ __launch_bounds__(kThreads) void k_gather_xrows(const T* __restrict__
       acc = x ? x[i] : T(0);
     else
       acc = xrows_sum(L[q]);
-    y[i] = accumulate ? y[i] + acc : acc;
+    const T yi = accumulate ? y[i] + acc : acc;
+    if constexpr (NTY)
+      __builtin_nontemporal_store(yi, y + i);
+    else
+      y[i] = yi;
   }
 }
 
@@ -471,44 +475,67 @@ hipError_t launch_gather_lattice(const T* yE, int nx, int ny, int nz, int p, int
 }
 template <typename T, int P>
 hipError_t gather_xrows_p(const T* yX, int nx, int ny, int nz, int constrained, int accumulate,
-                          const T* x, T* y, const int* skip, hipStream_t s, bool nt) {
+                          const T* x, T* y, const int* skip, hipStream_t s, bool nt, bool nt_y) {
   const int64_t nodes = ((int64_t)nx * P + 1) * ((int64_t)ny * P + 1) * ((int64_t)nz * P + 1);
   const int64_t per = (int64_t)kThreads * kXRowsNodes;
   const dim3 grid((unsigned)((nodes + per - 1) / per));
-  if (nt)
-    hipLaunchKernelGGL((k_gather_xrows<T, P, true>), grid, dim3(kThreads), 0, s, yX,
-                       xrows_geom(nx, ny, nz, P), constrained, accumulate, x, y, skip);
+  const XRowsGeom g = xrows_geom(nx, ny, nz, P);
+  if (nt && nt_y)
+    hipLaunchKernelGGL((k_gather_xrows<T, P, true, true>), grid, dim3(kThreads), 0, s, yX, g,
+                       constrained, accumulate, x, y, skip);
+  else if (nt)
+    hipLaunchKernelGGL((k_gather_xrows<T, P, true, false>), grid, dim3(kThreads), 0, s, yX, g,
+                       constrained, accumulate, x, y, skip);
+  else if (nt_y)
+    hipLaunchKernelGGL((k_gather_xrows<T, P, false, true>), grid, dim3(kThreads), 0, s, yX, g,
+                       constrained, accumulate, x, y, skip);
   else
-    hipLaunchKernelGGL((k_gather_xrows<T, P, false>), grid, dim3(kThreads), 0, s, yX,
-                       xrows_geom(nx, ny, nz, P), constrained, accumulate, x, y, skip);
+    hipLaunchKernelGGL((k_gather_xrows<T, P, false, false>), grid, dim3(kThreads), 0, s, yX, g,
+                       constrained, accumulate, x, y, skip);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int constrained,
                                int accumulate, const T* x, T* y, const int* skip, hipStream_t s,
-                               bool nt) {
+                               bool nt, bool nt_y) {
   const int64_t Lx = (int64_t)nx * p + 1, Ly = (int64_t)ny * p + 1, Lz = (int64_t)nz * p + 1;
   if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
   if (Lx * Ly * Lz > 0x7fffffff) return hipErrorInvalidValue;
   switch (p) {
-    case 1: return gather_xrows_p<T, 1>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 2: return gather_xrows_p<T, 2>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 3: return gather_xrows_p<T, 3>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 4: return gather_xrows_p<T, 4>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 5: return gather_xrows_p<T, 5>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 6: return gather_xrows_p<T, 6>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 7: return gather_xrows_p<T, 7>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
-    case 8: return gather_xrows_p<T, 8>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt);
+    case 1:
+      return gather_xrows_p<T, 1>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 2:
+      return gather_xrows_p<T, 2>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 3:
+      return gather_xrows_p<T, 3>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 4:
+      return gather_xrows_p<T, 4>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 5:
+      return gather_xrows_p<T, 5>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 6:
+      return gather_xrows_p<T, 6>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 7:
+      return gather_xrows_p<T, 7>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
+    case 8:
+      return gather_xrows_p<T, 8>(yX, nx, ny, nz, constrained, accumulate, x, y, skip, s, nt,
+                                   nt_y);
     default: return hipErrorInvalidValue;
   }
 }
 template hipError_t launch_gather_xrows<double>(const double*, int, int, int, int, int, int,
                                                 const double*, double*, const int*, hipStream_t,
-                                                bool);
+                                                bool, bool);
 template hipError_t launch_gather_xrows<float>(const float*, int, int, int, int, int, int,
                                                const float*, float*, const int*, hipStream_t,
-                                               bool);
+                                               bool, bool);
 template hipError_t launch_gather_lattice<double>(const double*, int, int, int, int, int, int,
                                                   const double*, double*, const int*, hipStream_t);
 template hipError_t launch_gather_lattice<float>(const float*, int, int, int, int, int, int,
