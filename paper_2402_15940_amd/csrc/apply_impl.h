@@ -45,7 +45,7 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 #define PAFEM_NE_BY_Q 1, 1, 1, 7, 4, 5, 7, 5, 1, 3, 1
 #endif
 #ifndef PAFEM_WAVES_DIFF_F64
-#define PAFEM_WAVES_DIFF_F64 1, 1, 1, 1, 4, 1, 1, 1, 1
+#define PAFEM_WAVES_DIFF_F64 1, 1, 1, 1, 3, 1, 1, 1, 1
 #endif
 constexpr int kNeByQ[] = {PAFEM_NE_BY_Q};
 // quadrature-data loads by p: 1 = non-temporal (streamed past the caches),
