@@ -380,7 +380,10 @@ hipError_t launch_gather_xrows(const T* yX, int nx, int ny, int nz, int p, int c
 // E-vector loads of the ordered sums, by p, for FP64 diffusion operators:
 // 1 = non-temporal, 0 = ordinary.  Measured on MI355X: non-temporal loads
 // shorten the p=6 FP64 diffusion apply by 5% and lengthen every other order,
-// the FP32 applies and the mass applies by 1-10%.
+// the FP32 applies and the mass applies by 1-10%.  The p=6 gain needs other
+// device memory to have been written before the first apply (other
+// quadrature data, the FP32 copy, any application data); in a process whose
+// only device writes were this operator's assembly they cost 4% instead.
 #ifndef PAFEM_NT_EVEC_DIFF64_BY_P
 #define PAFEM_NT_EVEC_DIFF64_BY_P 0, 0, 0, 0, 0, 0, 1, 0, 0
 #endif
