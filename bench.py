@@ -413,6 +413,32 @@ def serving_configs(pf, ctx, n_req, fracs, budget, slots, iters):
     return {"capacity_burst": burst, "runs": runs}
 
 
+def profile_run_fp32(torch, pf, ctx, p, steps):
+    """FP32 diffusion applies on FP32 and on bfloat16 quadrature data, each
+    launched `steps` times (after one warm-up) on a ~8M-dof mesh of order p."""
+    from paper_2402_15940_amd import inputs
+    N = inputs.mesh_n_for_dofs(p, 8e6)
+    v = inputs.perturbed_vertices(N, N, N, seed=inputs.mesh_seed(p, N))
+    sp = pf.Space(pf.Mesh(ctx, N, N, N, v), p)
+    K = pf.Operator(sp, pf.DIFFUSION)
+    K.assemble(pf.FP32 | pf.BF16)
+    x = torch.from_numpy(inputs.random_vector(sp.ndofs, inputs.vector_seed(p, N))).cuda().float()
+    y = torch.empty_like(x)
+    out = {"p": p, "N": N, "ndofs": sp.ndofs, "elements": sp.nelems}
+    ms, _ = time_applies(torch, K, x, y, steps, 1)
+    out["diffusion_fp32_apply_ms"] = round(ms, 5)
+    K.apply(x, y, bf16=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        K.apply(x, y, bf16=True)
+    e1.record()
+    torch.cuda.synchronize()
+    out["diffusion_bf16_data_apply_ms"] = round(e0.elapsed_time(e1) / steps, 5)
+    print(json.dumps({"profile_run_fp32": out}), flush=True)
+
+
 def profile_run(torch, pf, ctx, p, steps):
     """The kernels the counter summaries under profiles/ cover, each launched
     `steps` times (after one warm-up) on a ~8M-dof mesh of order p."""
@@ -489,6 +515,9 @@ def main():
     ap.add_argument("--scatter", choices=["atomic", "deterministic"], default="deterministic")
     ap.add_argument("--copy-only", action="store_true",
                     help="stop after the headline applies and the copy reference (profiling runs)")
+    ap.add_argument("--profile-fp32", type=int, default=0, metavar="P",
+                    help="profiling run at order P (~8M dofs): FP32 diffusion applies on FP32 and "
+                         "on bfloat16 quadrature data, --steps times each")
     ap.add_argument("--profile", type=int, default=0, metavar="P",
                     help="profiling run at order P (~8M dofs): FP64 diffusion apply, FP64 mass "
                          "apply, matrix-free diffusion apply, FP64 CG iterations, the diffusion "
@@ -510,6 +539,8 @@ def main():
     ctx = pf.Context(0)
     if args.profile:
         return profile_run(torch, pf, ctx, args.profile, args.steps)
+    if args.profile_fp32:
+        return profile_run_fp32(torch, pf, ctx, args.profile_fp32, args.steps)
     p = args.p
     N = inputs.mesh_n_for_dofs(p, args.dofs)
     n, q = p + 1, p + 2
